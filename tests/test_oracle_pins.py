@@ -1,0 +1,275 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle.
+
+Every test here runs on the CPU.  Each pins a part of the oracle to something
+fixed by the paper or by mathematics: the generic least-squares projection
+(Lemma 2), the literal three-matrix DR iteration (Section 3), exact optima
+(brute force, HiGHS, the monotone 1-D coupling, one-row/one-column and
+separable problems), the identities of the variational-representation lemma
+(Appendix B) and the optimality conditions of Proposition 1.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from gen import (assignment_instance, config_mixture_2d, config_small_fp64,
+                 line_instance, paper_protocol, quantise_marginal, round_to,
+                 separable_instance)
+from oracle import certify, dr3, exact, ref
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "exact_opt.json")
+
+
+def _rand_problem(rng, m, n, zeros=False):
+    C = rng.uniform(0.0, 1.0, (m, n))
+    wp = rng.uniform(0.0, 1.0, m)
+    wq = rng.uniform(0.0, 1.0, n)
+    if zeros and m > 1:
+        wp[rng.integers(0, m)] = 0.0
+    if zeros and n > 1:
+        wq[rng.integers(0, n)] = 0.0
+    return C, quantise_marginal(wp), quantise_marginal(wq)
+
+
+# --------------------------------------------------------------------------
+# Lemma 2: closed-form projection onto {X e = p, X^T f = q}
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("m,n", [(1, 1), (1, 5), (4, 1), (3, 3), (4, 6), (7, 5)])
+def test_lemma2_projection_equals_generic_projection(m, n):
+    rng = np.random.default_rng([100, m, n])
+    _, p, q = _rand_problem(rng, m, n)
+    W = rng.standard_normal((m, n))
+    P1 = dr3.project_lemma2(W, p, q)
+    P2 = dr3.project_lstsq(W, p, q)
+    np.testing.assert_allclose(P1, P2, atol=1e-13)
+    # exact marginals, idempotence, and W - P(W) in ran A* (= y e^T + f x^T)
+    np.testing.assert_allclose(P1.sum(1), p, atol=1e-14)
+    np.testing.assert_allclose(P1.sum(0), q, atol=1e-14)
+    np.testing.assert_allclose(dr3.project_lemma2(P1, p, q), P1, atol=1e-14)
+    D = W - P1
+    np.testing.assert_allclose(D - D[:, :1] - D[:1, :] + D[0, 0], 0.0, atol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# Algorithm 1 == the three-matrix DR of eq. (drot:general:form)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("m,n,scale,warm", [(3, 4, 50.0, False), (6, 6, 20.0, False),
+                                            (1, 5, 10.0, False), (5, 1, 10.0, False),
+                                            (8, 5, 40.0, True), (9, 12, 5.0, True)])
+def test_algorithm1_equals_three_matrix_dr(m, n, scale, warm):
+    rng = np.random.default_rng([101, m, n])
+    C, p, q = _rand_problem(rng, m, n, zeros=True)
+    rho = scale / (m + n)
+    phi0 = psi0 = None
+    Y0 = np.outer(p, q)
+    if warm:
+        phi0 = 0.01 * rng.standard_normal(m)
+        psi0 = 0.01 * rng.standard_normal(n)
+        Y0 = Y0 + phi0[:, None] + psi0[None, :]
+    K = 40
+    Xs, _, Ys = dr3.dr3_iterate(C, p, q, rho, K, Y0=Y0)
+    for k in (1, 2, 3, 10, K):
+        R = ref.solve(C, p, q, rho, 0.0, max_iter=k, phi0=phi0, psi0=psi0)
+        assert R.info["iters"] == k
+        np.testing.assert_allclose(R.X, Xs[k - 1], atol=1e-13, rtol=0)
+        Y = R.X + R.phi[:, None] + R.psi[None, :]
+        np.testing.assert_allclose(Y, Ys[k], atol=1e-13, rtol=0)
+        # accumulators: a_k = Y_k e - p, b_k = Y_k^T f - q
+        np.testing.assert_allclose(R.a, Ys[k].sum(1) - p, atol=1e-13)
+        np.testing.assert_allclose(R.b, Ys[k].sum(0) - q, atol=1e-13)
+        # alpha_k = f^T a_k / (m+n)
+        assert abs(R.info["alpha"] - R.a.sum() / (m + n)) < 1e-14
+
+
+def test_shift_sums_agree():
+    """f^T phi_k = e^T psi_k for k >= 1 (from the shift updates with equal mass)."""
+    inst = config_small_fp64(3, 30, 45)
+    for k in (1, 7, 200):
+        R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=k)
+        assert abs(R.phi.sum() - R.psi.sum()) < 1e-13 * max(1.0, abs(R.phi).sum())
+
+
+# --------------------------------------------------------------------------
+# Exact optima
+# --------------------------------------------------------------------------
+def _golden():
+    with open(GOLDEN) as fh:
+        return json.load(fh)
+
+
+@pytest.mark.parametrize("case", _golden()["brute_force"], ids=lambda c: f"n{c['n']}s{c['seed']}")
+def test_converges_to_brute_force_assignment(case):
+    inst = assignment_instance(case["seed"], case["n"])
+    # library solver and brute force agree (pins the golden value itself)
+    assert abs(exact.assignment_uniform(inst.C) - case["opt"]) < 1e-14
+    R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 1e-9, max_iter=2_000_000)
+    assert R.status == 0
+    assert abs(R.info["pobj"] - case["opt"]) <= 1e-7 * max(case["opt"], 1e-3)
+    assert R.X.min() >= 0.0
+
+
+@pytest.mark.parametrize("case", _golden()["lp"], ids=lambda c: f"{c['gen']}{c['m']}x{c['n']}s{c['seed']}")
+def test_converges_to_lp_optimum(case):
+    if case["gen"] == "config_small_fp64":
+        inst = config_small_fp64(case["seed"], case["m"], case["n"])
+    else:
+        inst = paper_protocol(case["seed"], case["m"])
+    # The relative stopping test bounds the objective error only up to a
+    # modest factor; pin convergence at a tight tolerance.
+    tol = 1e-8 if case["m"] * case["n"] <= 2500 else 1e-7
+    R = ref.solve(inst.C, inst.p, inst.q, inst.rho, tol, max_iter=5_000_000)
+    assert R.status == 0
+    assert abs(R.info["pobj"] - case["opt"]) / case["opt"] <= 20 * tol
+    # certified bracket from the oracle's own output contains the optimum
+    lb, ub = certify.bracket(inst.C, inst.p, inst.q, R.X, R.mu)
+    assert lb <= case["opt"] * (1 + 1e-12) and case["opt"] <= ub * (1 + 1e-12)
+
+
+def test_default_tolerance_objective_error():
+    """At its own stopping tolerance (1e-6) the small FP64 case lands within
+    a small multiple of the tolerance of the optimum."""
+    for seed in (0, 1):
+        inst = config_small_fp64(seed)
+        case = [c for c in _golden()["lp"] if c["m"] == 100 and c["seed"] == seed][0]
+        R = ref.solve_instance(inst, max_iter=2_000_000)
+        assert R.status == 0 and R.info["eps_p"] <= 1e-6 and R.info["eps_g"] <= 1e-6
+        assert abs(R.info["pobj"] - case["opt"]) / case["opt"] <= 5e-6
+
+
+@pytest.mark.parametrize("case", _golden()["line"], ids=lambda c: f"{c['m']}x{c['n']}")
+def test_converges_to_monotone_coupling_on_a_line(case):
+    # Line problems are badly conditioned for DR (slow tail); the larger one
+    # is pinned at a looser tolerance to keep the CPU suite short.
+    inst = line_instance(case["seed"], case["m"], case["n"], rho0=2.0)
+    tol = 1e-8 if case["m"] * case["n"] <= 2400 else 1e-6
+    R = ref.solve(inst.C, inst.p, inst.q, inst.rho, tol, max_iter=3_000_000)
+    assert R.status == 0
+    assert abs(R.info["pobj"] - case["opt"]) / case["opt"] <= 20 * tol
+
+
+def test_single_row_and_single_column():
+    rng = np.random.default_rng(7)
+    C, p, q = _rand_problem(rng, 1, 9)
+    R = ref.solve(C, p, q, 2.0 / 10, 1e-12, max_iter=200_000)
+    np.testing.assert_allclose(R.X[0], q, atol=1e-11)
+    assert abs(R.info["pobj"] - exact.single_row(C, q)) < 1e-11
+    C, p, q = _rand_problem(rng, 9, 1)
+    R = ref.solve(C, p, q, 2.0 / 10, 1e-12, max_iter=200_000)
+    np.testing.assert_allclose(R.X[:, 0], p, atol=1e-11)
+    assert abs(R.info["pobj"] - exact.single_col(C, p)) < 1e-11
+
+
+def test_separable_cost():
+    inst = separable_instance(0, 30, 20)
+    R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 1e-10, max_iter=500_000)
+    opt = exact.separable(inst.meta["g"], inst.meta["h"], inst.p, inst.q)
+    assert abs(R.info["pobj"] - opt) / opt < 1e-8
+
+
+def test_hand_solved_two_by_two():
+    """C = [[1,3],[2,5]], p = (0.4,0.6), q = (0.7,0.3).  Feasible plans are
+    [[a, .4-a], [.7-a, a-.1]] with a in [.1,.4] and cost a + 2.1, so the
+    optimum is a = 0.1, X* = [[.1,.3],[.6,0]], OPT = 2.2."""
+    C = np.array([[1.0, 3.0], [2.0, 5.0]])
+    p = np.array([0.4, 0.6])
+    q = np.array([0.7, 0.3])
+    R = ref.solve(C, p, q, 0.5, 1e-12, max_iter=1_000_000)
+    assert abs(R.info["pobj"] - 2.2) < 1e-10
+    np.testing.assert_allclose(R.X, [[0.1, 0.3], [0.6, 0.0]], atol=1e-9)
+
+
+# --------------------------------------------------------------------------
+# Appendix B (variational representation) and Proposition 1
+# --------------------------------------------------------------------------
+def test_variational_identities_each_iteration():
+    """For every k: <C,X_{k+1}> - p.mu_{k+1} - q.nu_{k+1} = -<Y_{k+1}, Y_{k+1}-Y_k>/rho,
+    mu_{k+1} e^T + f nu_{k+1}^T - C <= (Y_{k+1}-Y_k)/rho, and
+    ||Y_{k+1}-Y_k|| is non-increasing (T is firmly non-expansive)."""
+    inst = config_small_fp64(2, 12, 9)
+    C, p, q, rho = inst.C, inst.p, inst.q, inst.rho * 20
+    Yprev = np.outer(p, q)
+    step_prev = np.inf
+    for k in range(1, 60):
+        R = ref.solve(C, p, q, rho, 0.0, max_iter=k)
+        Y = R.X + R.phi[:, None] + R.psi[None, :]
+        mu, nu = R.phi / rho, R.psi / rho
+        lhs = (C * R.X).sum() - p @ mu - q @ nu
+        rhs = -(Y * (Y - Yprev)).sum() / rho
+        assert abs(lhs - rhs) <= 1e-10 * max(1.0, abs(rhs))
+        assert np.all(mu[:, None] + nu[None, :] - C <= (Y - Yprev) / rho + 1e-9)
+        step = np.linalg.norm(Y - Yprev)
+        assert step <= step_prev * (1 + 1e-12) + 1e-15
+        step_prev = step
+        Yprev = Y
+
+
+def test_converged_pair_satisfies_proposition_1():
+    inst = config_small_fp64(4, 40, 30)
+    R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 1e-9, max_iter=2_000_000)
+    ev = ref.evaluate(inst.C, inst.p, inst.q, inst.rho, R.X, R.phi, R.psi)
+    assert R.X.min() >= 0                                   # (i) X >= 0
+    assert ev["eps_p"] < 1e-8                               # (i) marginals
+    assert ev["r_dual"] < 1e-7                              # (ii) dual feasibility
+    assert ev["gap"] / ev["pobj"] < 1e-8                    # (iii) zero gap
+    # Few entries stay positive at a vertex of the transport polytope.
+    assert (R.X > 1e-9).sum() <= 2 * (40 + 30)
+
+
+# --------------------------------------------------------------------------
+# Stopping-test bookkeeping
+# --------------------------------------------------------------------------
+def test_trace_matches_direct_evaluation_with_lagged_dual_residual():
+    inst = config_small_fp64(5, 25, 31)
+    K = 50
+    Rk = ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=K, trace=True)
+    Rk1 = ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=K - 1)
+    ev = ref.evaluate(inst.C, inst.p, inst.q, inst.rho, Rk.X, Rk.phi, Rk.psi)
+    ev_prev = ref.evaluate(inst.C, inst.p, inst.q, inst.rho, Rk1.X, Rk1.phi, Rk1.psi)
+    last = dict(zip(ref.TRACE_FIELDS, Rk.trace[-1]))
+    # r_primal and gap are at iterate K, r_dual at the shifts entering iteration K
+    assert abs(last["r_primal"] - np.sqrt(((Rk.X.sum(1) - inst.p) ** 2).sum()
+                                          + ((Rk.X.sum(0) - inst.q) ** 2).sum())) < 1e-15
+    assert abs(last["r_primal"] - ev["r_primal"]) < 1e-15
+    assert abs(last["gap"] - ev["gap"]) < 1e-14
+    assert abs(last["r_dual_lag"] - ev_prev["r_dual"]) < 1e-12 * max(1, ev_prev["r_dual"])
+
+
+def test_stop_is_first_iterate_meeting_tolerance():
+    inst = config_small_fp64(6, 20, 20)
+    R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 1e-4, max_iter=100_000, trace=True)
+    assert R.status == 0
+    me = R.trace[:, 5]
+    assert me[-1] <= 1e-4 and np.all(me[:-1] > 1e-4)
+
+
+def test_maxiter_status():
+    inst = config_small_fp64(0, 10, 10)
+    R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 1e-12, max_iter=3)
+    assert R.status == 1 and R.info["iters"] == 3
+
+
+# --------------------------------------------------------------------------
+# FP32-rounded inputs and the certificate on a mid-size instance
+# --------------------------------------------------------------------------
+@pytest.mark.slow
+def test_rounded_midsize_instance_bracket():
+    inst = round_to(config_mixture_2d(0, 128, 160), np.float32)
+    R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 1e-4, max_iter=400_000)
+    assert R.status == 0
+    lb, ub = certify.bracket(inst.C, inst.p, inst.q, R.X, R.mu)
+    opt = exact.lp_highs(inst.C, inst.p, inst.q)[0]
+    assert lb <= opt * (1 + 1e-12) and opt <= ub * (1 + 1e-12)
+    assert (ub - lb) / ub < 1e-3
+    assert abs(R.info["pobj"] - opt) / opt < 1e-3
+
+
+def test_paper_protocol_assignment_accuracy():
+    """The paper's accuracy experiment: uniform marginals, rho0 = 2, stop on
+    constraint violation; objective within 1e-3 of the assignment optimum
+    (qualitative check: the paper prints no numbers)."""
+    inst = paper_protocol(0, 128)
+    opt = exact.assignment_uniform(inst.C)
+    R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 1e-4, max_iter=100_000)
+    assert R.status == 0
+    assert abs(R.info["pobj"] - opt) / opt < 1e-3
