@@ -1,0 +1,229 @@
+"""Benchmark of the DROT hot path on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-large] [--no-cpu]
+                    [--no-tol] [--tile-rows R] [--tile-chunks H] [--check-every G]
+
+A step is one DROT iteration (Algorithm 1): the fused sweep over the dense
+m x n plan plus the O(m+n) dual update and the stopping test.  The timed
+workload is the 4096 x 4096 float32 problem (2-D five-Gaussian point clouds,
+squared-Euclidean cost normalised to max 1, Dirichlet(1) marginals,
+rho = (1/ln m)/(m+n)), resident in HBM before timing starts.  One JSON line
+is printed with iterations/s (`value`), the roofline of the sweep kernel
+(timed with hipEvents around every sweep launch of the timed region), the
+time to the 1e-4 relative stopping test, the 20000 x 20000 roofline instance
+and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E peak
+BYTES_PER_ENTRY_F32 = 12     # read X, write X, read C (float32)
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_instance(m, n, upcast=True):
+    """The mixture2d instance rounded to float32 (C kept as float32 when
+    `upcast` is False, which the large instance uses to save host memory)."""
+    import numpy as np
+    from gen import config_mixture_2d, round_to
+    t0 = time.time()
+    inst = config_mixture_2d(0, m, n, seed_tag=2 if m == n == 4096 else 3)
+    if upcast:
+        inst = round_to(inst, np.float32)
+    else:
+        inst.C = inst.C.astype(np.float32)
+    log(f"generated {inst.name} in {time.time() - t0:.1f}s")
+    return inst
+
+
+def upload(inst):
+    import torch
+    dev = torch.device("cuda:0")
+    C = torch.from_numpy(inst.C.astype("float32", copy=False)).to(dev)
+    p = torch.from_numpy(inst.p.astype("float32")).to(dev)
+    q = torch.from_numpy(inst.q.astype("float32")).to(dev)
+    return C, p, q
+
+
+def timed_iterations(ctx, C, p, q, rho, steps, warmup, args, timed_events=True):
+    """Bind, warm up, then time exactly `steps` iterations.  Returns
+    (seconds, sweep_ms_avg or None, sweep_count)."""
+    import torch
+    from paper_2110_11738_amd import drot
+    m, n = C.shape
+    X = torch.empty((m, n), dtype=C.dtype, device=C.device)
+    flags = drot.FLAG_TIME_SWEEP if timed_events else 0
+    prm = drot.make_params(rho, 0.0, warmup + steps + 1, check_every=args.check_every,
+                           flags=flags, tile_rows=args.tile_rows, tile_chunks=args.tile_chunks)
+    ctx.bind(C, p, q, X, prm)
+    if warmup:
+        ctx.iterate(warmup)
+    torch.cuda.synchronize()
+    before = ctx.finish()  # cheap final pass, resets nothing; gives sweep counters so far
+    ms0, n0 = before["sweep_ms_total"], before["sweep_timed"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.iterate(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    res = ctx.finish()
+    assert res["iters"] == warmup + steps, res
+    cnt = res["sweep_timed"] - n0
+    avg = (res["sweep_ms_total"] - ms0) / cnt if cnt > 0 else None
+    return t1 - t0, avg, cnt, res
+
+
+def cpu_baseline(inst, budget_s=20.0):
+    """Time the FP64 oracle per iteration on a bounded sample of iterations."""
+    import numpy as np
+    from oracle import ref
+    m, n = inst.m, inst.n
+    t0 = time.perf_counter()
+    ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=1)
+    t_one = time.perf_counter() - t0
+    k = max(2, int(budget_s / max(t_one / 2, 1e-3)))
+    k = min(k, 200)
+    t0 = time.perf_counter()
+    ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=1 + k)
+    t_k = time.perf_counter() - t0
+    per_iter = (t_k - t_one) / k
+    del np
+    return {"value": 1.0 / per_iter, "unit": "iter/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle/drot_ref.c (FP64, single thread) on the same {m}x{n} instance "
+                      f"upcast from float32: ({1 + k} - 1) iterations from X0 = p q^T, "
+                      f"initialisation time subtracted; {t_k:.1f}s of CPU work",
+            "host_cpu": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--m", type=int, default=4096)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--large", type=int, default=20000, help="side of the roofline instance (0 = skip)")
+    ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tol", action="store_true")
+    ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--tile-chunks", type=int, default=0)
+    ap.add_argument("--check-every", type=int, default=64)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the DROT sweep of this build runs on a single "
+              "MI355X (multi-GPU row sharding is a design note, not built). Use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2110_11738_amd import drot
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    drot.lib()
+    ctx = drot.Context(0)
+
+    # ---- main workload: 4096^2 float32 -------------------------------------
+    inst = make_instance(args.m, args.n)
+    C, p, q = upload(inst)
+    m, n = args.m, args.n
+    log(f"timing {args.steps} iterations after {args.warmup} warm-up iterations")
+    secs, sweep_ms, cnt, res = timed_iterations(ctx, C, p, q, inst.rho, args.steps, args.warmup, args)
+    value = args.steps / secs
+    secs_ne, _, _, _ = timed_iterations(ctx, C, p, q, inst.rho, args.steps, args.warmup, args,
+                                        timed_events=False)
+    alg_bytes = BYTES_PER_ENTRY_F32 * m * n
+    achieved = alg_bytes / (sweep_ms * 1e-3) / 1e9 if sweep_ms else None
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+            "kernel": "sweep_kernel<float,iter>", "bytes_per_launch": alg_bytes,
+            "avg_launch_us": sweep_ms * 1e3 if sweep_ms else None, "launches_timed": cnt}
+    log(f"{value:.1f} it/s ({1e3 * secs / args.steps:.4f} ms/it); sweep {sweep_ms * 1e3:.2f} us "
+        f"-> {achieved:.0f} GB/s; without events {args.steps / secs_ne:.1f} it/s")
+
+    out = {
+        "metric": "DROT iters/s + time-to-1e-4 residual at 4096^2 and 20000^2; HBM GB/s vs peak",
+        "value": value, "unit": "iter/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * secs / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"DROT mixture2d {m}x{n} float32 (two 2-D 5-Gaussian clouds, "
+                               f"sigma 0.1, sq-Euclidean C / max, Dirichlet(1) marginals, "
+                               f"rho0 = 1/ln m)", "m": m, "n": n, "rho": inst.rho,
+                   "tile_rows": args.tile_rows, "tile_chunks": args.tile_chunks,
+                   "check_every": args.check_every, "parallelism": "single GPU"},
+        "value_without_sweep_events": args.steps / secs_ne,
+        "roofline": roof,
+    }
+
+    # ---- time to the 1e-4 relative stopping test -----------------------------
+    if not args.no_tol:
+        X = torch.empty((m, n), dtype=torch.float32, device="cuda")
+        prm = drot.make_params(inst.rho, 1e-4, 2_000_000, check_every=args.check_every,
+                               tile_rows=args.tile_rows, tile_chunks=args.tile_chunks)
+        X, r = ctx.solve(C, p, q, prm, X=X)
+        torch.cuda.synchronize()
+        out["time_to_tol"] = {"tol": 1e-4, "status": r["status"], "iters": r["iters"],
+                              "seconds_device": r["seconds_to_tol"],
+                              "seconds_host": r["seconds_total"],
+                              "objective": r["objective"], "eps_primal": r["eps_primal"],
+                              "eps_dual": r["eps_dual"], "eps_gap": r["eps_gap"]}
+        log(f"time to 1e-4: {r['iters']} iterations, {r['seconds_to_tol']:.3f}s device, "
+            f"{r['seconds_total']:.3f}s host, status {r['status']}")
+        del X
+
+    # ---- CPU oracle baseline ----------------------------------------------------
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(inst)
+        log(f"cpu oracle {out['cpu_baseline']['value']:.3f} it/s")
+
+    # ---- 20000^2 roofline instance ----------------------------------------------
+    if not args.no_large and args.large > 0:
+        del C, p, q
+        torch.cuda.empty_cache()
+        L = args.large
+        linst = make_instance(L, L, upcast=False)
+        C, p, q = upload(linst)
+        rho_l = linst.rho
+        del linst
+        ksteps, kwarm = 40, 5
+        secs_l, sweep_l, cnt_l, _ = timed_iterations(ctx, C, p, q, rho_l, ksteps, kwarm, args)
+        ab = BYTES_PER_ENTRY_F32 * L * L
+        ach = ab / (sweep_l * 1e-3) / 1e9
+        out["large"] = {"m": L, "n": L, "iter_per_s": ksteps / secs_l,
+                        "ms_per_iter": 1e3 * secs_l / ksteps,
+                        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                                     "bytes_per_launch": ab, "avg_launch_us": sweep_l * 1e3,
+                                     "launches_timed": cnt_l}}
+        log(f"{L}^2: {ksteps / secs_l:.1f} it/s, sweep {sweep_l * 1e3:.1f} us -> {ach:.0f} GB/s "
+            f"({100 * ach / HBM_PEAK_GBS:.1f}% of peak)")
+
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -76,8 +76,10 @@ class Instance:
 
 
 def rho_runtime(m: int, n: int) -> float:
-    """rho0 = 1/ln(m) divided by (m+n): the runtime-experiment step size."""
-    return (1.0 / math.log(m)) / (m + n)
+    """rho0 = 1/ln(m) divided by (m+n): the runtime-experiment step size.
+    (m is clamped to 3 so that degenerate one- and two-row test problems
+    still get a finite positive step.)"""
+    return (1.0 / math.log(max(m, 3))) / (m + n)
 
 
 def rho_accuracy(m: int, n: int, rho0: float = 2.0) -> float:

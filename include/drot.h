@@ -1,0 +1,192 @@
+/*
+ * drot.h -- C ABI of the MI355X (gfx950) DROT library, libdrot.so.
+ *
+ * DROT is Douglas-Rachford splitting applied to the discrete optimal transport
+ * linear program (Mai, Lindbaeck, Johansson, "A Fast and Accurate Splitting
+ * Method for Optimal Transport: Analysis and Implementation"):
+ *
+ *     minimise <C, X>  subject to  X 1_n = p,  X^T 1_m = q,  X >= 0     (eq. 1)
+ *
+ * with C (m x n) >= 0 and p, q nonnegative with equal total mass.  The library
+ * runs Algorithm 1 of the paper on the GPU: one fused pass over the dense
+ * m x n plan per iteration (clamped X-update with the row shift phi, the
+ * column shift psi and the cost term; row sums, column sums, <C,X> and the
+ * dual-residual partial in the same pass), followed by the O(m+n) shift and
+ * accumulator update and the primal-dual stopping test of Section 3
+ * ("Stopping criteria").
+ *
+ * Conventions for every entry point
+ *  - All array arguments are DEVICE pointers on the context's GPU, owned by the
+ *    caller (for example the storage of torch tensors).  The library never
+ *    frees or keeps them beyond the documented lifetime.  `drot_result` and
+ *    the host buffers of drot_get_trace are HOST memory.
+ *  - Matrices are row-major: entry (i, j) of X lives at X[i * ldx + j]
+ *    (row i = source i with mass p_i, column j = target j with mass q_j).
+ *  - Element type: `dtype` selects float (DROT_F32) or double (DROT_F64) for
+ *    C, X, p and q.  Dual outputs and warm starts (mu, nu) are always double.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).
+ *    drot_solve blocks the calling host thread until the stopping test is met
+ *    (it polls a device flag every `check_every` iterations).
+ *  - No exceptions cross the ABI.  Every entry point returns a drot_status;
+ *    on error a message is available from drot_last_error() (thread-local).
+ *    Argument errors are detected before any GPU work is enqueued; errors that
+ *    need the data (unequal mass, non-finite input) are detected by the
+ *    initialisation pass, before the first iteration.
+ *  - A context is not thread-safe: use one context per host thread.  Calls on
+ *    one context must not overlap.
+ */
+#ifndef DROT_H
+#define DROT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct drot_ctx drot_ctx;
+
+typedef enum {
+  DROT_OK = 0,            /* stopping test met; outputs valid */
+  DROT_MAXITER = 1,       /* max_iter reached first; outputs valid */
+  DROT_EINVAL = -1,       /* invalid argument (size, leading dim, pointer, parameter) */
+  DROT_EMASS = -2,        /* negative marginal entry or sum(p) != sum(q) */
+  DROT_ENONFINITE = -3,   /* NaN/Inf in the inputs or in the iteration */
+  DROT_ENOMEM = -4,       /* workspace allocation failed */
+  DROT_EDEVICE = -5,      /* no usable GPU, or a HIP runtime error */
+  DROT_EUNSUPPORTED = -6, /* valid but unsupported combination */
+  DROT_ESTATE = -7        /* call out of order (e.g. iterate before bind) */
+} drot_status;
+
+typedef enum { DROT_F32 = 0, DROT_F64 = 1 } drot_dtype;
+
+/* Stopping-test modes (Section 3, "Stopping criteria").  With
+ *   r_primal = sqrt(|X e - p|^2 + |X^T f - q|^2),
+ *   r_dual   = |[mu e^T + f nu^T - C]_+|_F,  mu = phi/rho, nu = psi/rho,
+ *   gap      = |<C,X> - (p.mu + q.nu)|,
+ * DROT_TOL_RELATIVE stops when max(r_primal / sqrt(|p|^2+|q|^2),
+ * r_dual / |C|_F, gap / max(|<C,X>|, |p.mu+q.nu|)) <= tol, and
+ * DROT_TOL_ABSOLUTE when max(r_primal, r_dual, gap) <= tol.  During the
+ * iteration r_dual is the value at the shifts that entered the current
+ * update (it is computed from the same read of C), one iteration behind
+ * r_primal and gap; drot_finish reports all three at the returned pair. */
+typedef enum { DROT_TOL_RELATIVE = 0, DROT_TOL_ABSOLUTE = 1 } drot_tol_mode;
+
+/* Initial plan.  DROT_X0_PQ: X_0 = p q^T (the paper's experiments).
+ * DROT_X0_GIVEN: X holds X_0 on entry (any nonnegative matrix). */
+typedef enum { DROT_X0_PQ = 0, DROT_X0_GIVEN = 1 } drot_x0_mode;
+
+/* drot_params.flags */
+#define DROT_FLAG_NO_GRAPH 0x1    /* launch eagerly instead of replaying hipGraphs */
+#define DROT_FLAG_TIME_SWEEP 0x2  /* bracket sweep launches with hipEvents (see drot_result) */
+
+typedef struct {
+  double rho;          /* penalty parameter rho > 0 (the paper uses rho0/(m+n)) */
+  double tol;          /* stopping tolerance >= 0; 0 runs exactly max_iter iterations */
+  int64_t max_iter;    /* iteration cap >= 1 */
+  int32_t tol_mode;    /* drot_tol_mode */
+  int32_t x0_mode;     /* drot_x0_mode */
+  int32_t check_every; /* iterations between host polls of the stop flag; 0 = 32 */
+  int32_t flags;       /* DROT_FLAG_* */
+  int32_t tile_rows;   /* rows per workgroup tile of the sweep; 0 = automatic */
+  int32_t tile_chunks; /* 16-byte column chunks per lane (1 or 2); 0 = automatic */
+} drot_params;
+
+typedef struct {
+  int64_t iters;          /* iterations executed (K; X holds X_K) */
+  int32_t status;         /* DROT_OK or DROT_MAXITER (or the error code) */
+  int32_t reserved;
+  double objective;       /* <C, X_K>, accumulated in FP64 over the returned X */
+  double dual_objective;  /* p.mu + q.nu at the returned duals */
+  double r_primal, r_dual, gap;          /* exact, at the returned (X, mu, nu) */
+  double eps_primal, eps_dual, eps_gap;  /* the relative forms of the three */
+  double seconds_to_tol;  /* device clock, start of initialisation to the end of
+                             the iteration that met the test (or the last one) */
+  double seconds_total;   /* host wall clock of the call */
+  double sweep_ms_total;  /* with DROT_FLAG_TIME_SWEEP: summed hipEvent time of
+                             the timed sweep launches, else 0 */
+  int64_t sweep_timed;    /* number of sweep launches in sweep_ms_total */
+} drot_result;
+
+/* ---- library and context -------------------------------------------- */
+
+/* Version string, static storage. */
+const char *drot_version(void);
+
+/* Static description of a status code. */
+const char *drot_strerror(int status);
+
+/* Detail of the last error raised on the calling host thread ("" if none). */
+const char *drot_last_error(void);
+
+/* Create a context on HIP device `device` (0-based).  The context owns the
+ * workspace (grown on demand, kept between solves), the pinned host mirror of
+ * the device state and the captured graphs.  Returns DROT_EDEVICE when no GPU
+ * is usable, DROT_ENOMEM on allocation failure. */
+int drot_ctx_create(drot_ctx **ctx, int device);
+
+/* Destroy a context and release everything it owns.  NULL is accepted. */
+int drot_ctx_destroy(drot_ctx *ctx);
+
+/* ---- one-call solve (the paper's problem statement) ------------------ */
+
+/* Solve eq. (1) with DROT (Algorithm 1) from X_0 until the stopping test or
+ * params->max_iter.
+ *   m, n      problem size, m >= 1, n >= 1
+ *   dtype     drot_dtype of C, X, p, q
+ *   C, ldc    cost matrix, m x n, leading dimension ldc >= n, entries >= 0
+ *   p, q      marginals (length m and n), >= 0, sum(p) == sum(q) within
+ *             8 * machine epsilon of the dtype (relative); never renormalised
+ *   X, ldx    in/out plan, m x n, ldx >= n; on return X_K (never X - rho C).
+ *             Read as X_0 when params->x0_mode == DROT_X0_GIVEN.
+ *   mu, nu    optional outputs (double, length m and n): mu = phi_K / rho,
+ *             nu = psi_K / rho, the implicit dual variables (eq. dual:var)
+ *   mu0, nu0  optional warm start (double, length m and n, both or neither):
+ *             the iteration starts from the shifts phi_0 = rho mu0,
+ *             psi_0 = rho nu0 instead of zero; NULL = cold start
+ *   out       host result record (required)
+ * C, p, q are only read; C and X must not overlap. */
+int drot_solve(drot_ctx *ctx, int64_t m, int64_t n, int dtype, const void *C, int64_t ldc,
+               const void *p, const void *q, const drot_params *params, void *X, int64_t ldx,
+               double *mu, double *nu, const double *mu0, const double *nu0, drot_result *out,
+               void *stream);
+
+/* ---- step-wise interface (same computation, split at its natural seams) -- */
+
+/* Bind a problem to the context and run the initialisation of Algorithm 1
+ * (X_0, phi_0, psi_0, a_0, b_0, alpha_0) plus the scale factors of the
+ * relative stopping test.  Arguments as for drot_solve.  The pointers must
+ * stay valid until the next bind or the context's destruction.  Blocks until
+ * the initialisation pass has validated the data. */
+int drot_bind(drot_ctx *ctx, int64_t m, int64_t n, int dtype, const void *C, int64_t ldc,
+              const void *p, const void *q, const drot_params *params, void *X, int64_t ldx,
+              const double *mu0, const double *nu0, void *stream);
+
+/* Enqueue `iters` further iterations of Algorithm 1 (one sweep and one dual
+ * update each) on `stream` without waiting.  Iterations after the stopping
+ * test (or max_iter) has fired are no-ops on the device. */
+int drot_iterate(drot_ctx *ctx, int64_t iters, void *stream);
+
+/* Wait for `stream` and report progress: iterations done so far and whether
+ * the stop flag is set (1) or not (0). */
+int drot_poll(drot_ctx *ctx, int64_t *iters_done, int32_t *stopped, void *stream);
+
+/* Final evaluation pass: exact residuals, objectives and gap of the current
+ * (X, mu, nu), accumulated in FP64; writes mu and nu if non-NULL and fills
+ * `out`.  Blocks until done. */
+int drot_finish(drot_ctx *ctx, double *mu, double *nu, drot_result *out, void *stream);
+
+/* Copy per-iteration records of the last bound problem to host memory.
+ * Record k (1-based iteration index) holds 8 doubles:
+ *   pobj, dobj, r_primal, r_dual (lagged, see drot_tol_mode), gap,
+ *   test value (the quantity compared with tol), device seconds since the
+ *   start of initialisation, k.
+ * Only the last `trace capacity` iterations are kept (65536); asking for an
+ * older or a future record returns DROT_EINVAL. */
+int drot_get_trace(drot_ctx *ctx, int64_t first, int64_t count, double *host_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DROT_H */

@@ -1,0 +1,584 @@
+// Host side of libdrot.so: the C ABI of include/drot.h.
+//
+// Validation, the per-context workspace, the iteration driver (hipGraphs of
+// `check_every` iterations replayed on the caller's stream, early exit on the
+// device stop flag), polling, the final evaluation and error reporting.
+// Every computation of the method runs in the kernels of drot_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/drot.h"
+#include "drot_internal.h"
+
+using namespace drot;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(DROT_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Geometry {
+  int vec = 1, chunks = 1;
+  SweepGeom g{};
+  int n_tiles = 0;
+  int row_blocks = 0, col_blocks = 0;
+};
+
+}  // namespace
+
+struct drot_ctx {
+  int device = 0;
+  hipStream_t cap_stream = nullptr;  // private stream used only for capture
+  double wall_rate = 1e8;
+
+  // Workspace (one allocation, carved up per bind).
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  DevState* st = nullptr;        // device
+  DevState* st_host = nullptr;   // pinned mirror
+  double* trace = nullptr;
+
+  // Bound problem.
+  bool bound = false;
+  int dtype = 0;
+  drot_params prm{};
+  Geometry geo;
+  SweepArgs sa{};
+  AuxArgs aa{};
+  bool finished = false;
+
+  // Graph of `check_every` iterations.
+  hipGraphExec_t gexec = nullptr;
+  int g_iters = 0;
+  bool g_timed = false;
+
+  // Sweep timing (DROT_FLAG_TIME_SWEEP).
+  std::vector<hipEvent_t> ev;
+  double sweep_ms = 0.0;
+  int64_t sweep_n = 0;
+};
+
+namespace {
+
+void drop_graph(drot_ctx* c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  c->gexec = nullptr;
+  c->g_iters = 0;
+}
+
+int choose_geometry(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, const void* X,
+                    int64_t ldx, const drot_params* p, Geometry* out) {
+  const size_t es = dtype == DROT_F32 ? 4 : 8;
+  const int V = (int)(16 / es);
+  const bool aligned = ((uintptr_t)C % 16 == 0) && ((uintptr_t)X % 16 == 0) && (ldc % V == 0) &&
+                       (ldx % V == 0) && (n % V == 0);
+  Geometry g;
+  if (aligned) {
+    g.vec = V;
+    g.chunks = p->tile_chunks > 0 ? p->tile_chunks : 2;
+    if (g.chunks != 1 && g.chunks != 2)
+      return fail(DROT_EINVAL, "tile_chunks must be 0, 1 or 2 (got %d)", p->tile_chunks);
+  } else {
+    g.vec = 1;
+    g.chunks = p->tile_chunks == 1 ? 1 : 4;
+  }
+  const int64_t W = (int64_t)kWave * g.vec * g.chunks;
+  const int64_t n_ct = (n + W - 1) / W;
+  int rows = p->tile_rows;
+  if (rows < 0 || rows > 4096) return fail(DROT_EINVAL, "tile_rows must be in [0, 4096]");
+  if (rows == 0) {
+    // Enough tiles to fill 256 CUs several times over, but tall enough to keep
+    // the level-2 column-partial traffic near 1% of the sweep's.
+    rows = 256;
+    while (rows > 16 && ((m + rows - 1) / rows) * n_ct < 1024) rows /= 2;
+  }
+  const int64_t n_rb = (m + rows - 1) / rows;
+  if (n_ct * n_rb > 0x7fffffffLL) return fail(DROT_EUNSUPPORTED, "too many tiles");
+  g.g.m = m;
+  g.g.n = n;
+  g.g.ldc = ldc;
+  g.g.ldx = ldx;
+  g.g.n_ct = (int)n_ct;
+  g.g.n_rb = (int)n_rb;
+  g.g.rows = rows;
+  g.n_tiles = (int)(n_ct * n_rb);
+  g.row_blocks = (int)((m + kAuxBlock - 1) / kAuxBlock);
+  g.col_blocks = (int)((n + kAuxBlock - 1) / kAuxBlock);
+  *out = g;
+  return DROT_OK;
+}
+
+int validate(int64_t m, int64_t n, int dtype, const void* C, int64_t ldc, const void* p,
+             const void* q, const drot_params* prm, void* X, int64_t ldx, const double* mu0,
+             const double* nu0) {
+  if (m < 1 || n < 1) return fail(DROT_EINVAL, "m and n must be >= 1 (got %lld, %lld)",
+                                  (long long)m, (long long)n);
+  if (dtype != DROT_F32 && dtype != DROT_F64) return fail(DROT_EINVAL, "unknown dtype %d", dtype);
+  if (ldc < n || ldx < n) return fail(DROT_EINVAL, "leading dimensions must be >= n");
+  if (!prm) return fail(DROT_EINVAL, "params is NULL");
+  if (!(prm->rho > 0) || !std::isfinite(prm->rho))
+    return fail(DROT_EINVAL, "rho must be positive and finite");
+  if (!(prm->tol >= 0) || !std::isfinite(prm->tol))
+    return fail(DROT_EINVAL, "tol must be >= 0 and finite");
+  if (prm->max_iter < 1) return fail(DROT_EINVAL, "max_iter must be >= 1");
+  if (prm->tol_mode != DROT_TOL_RELATIVE && prm->tol_mode != DROT_TOL_ABSOLUTE)
+    return fail(DROT_EINVAL, "unknown tol_mode %d", prm->tol_mode);
+  if (prm->x0_mode != DROT_X0_PQ && prm->x0_mode != DROT_X0_GIVEN)
+    return fail(DROT_EINVAL, "unknown x0_mode %d", prm->x0_mode);
+  if (prm->check_every < 0) return fail(DROT_EINVAL, "check_every must be >= 0");
+  if (prm->flags & ~(DROT_FLAG_NO_GRAPH | DROT_FLAG_TIME_SWEEP))
+    return fail(DROT_EINVAL, "unknown flags 0x%x", prm->flags);
+  if (!C || !p || !q || !X) return fail(DROT_EINVAL, "C, p, q and X must be non-NULL");
+  if ((mu0 == nullptr) != (nu0 == nullptr))
+    return fail(DROT_EINVAL, "mu0 and nu0 must be given together");
+  const size_t es = dtype == DROT_F32 ? 4 : 8;
+  if ((uintptr_t)C % es || (uintptr_t)X % es || (uintptr_t)p % es || (uintptr_t)q % es)
+    return fail(DROT_EINVAL, "arrays must be aligned to their element size");
+  // Overlap of C and X (both m x n with their leading dimensions).
+  const uintptr_t c0 = (uintptr_t)C, c1 = c0 + (size_t)((m - 1) * ldc + n) * es;
+  const uintptr_t x0 = (uintptr_t)X, x1 = x0 + (size_t)((m - 1) * ldx + n) * es;
+  if (c0 < x1 && x0 < c1) return fail(DROT_EINVAL, "C and X overlap");
+  return DROT_OK;
+}
+
+int ensure_workspace(drot_ctx* c, int64_t m, int64_t n, const Geometry& g, size_t* offs) {
+  // offsets: st, trace, colpart, rowpart, tiles, a, b, phi64, psi64, phiT, psiT, blockpart
+  size_t o = 0;
+  offs[0] = o; o += up(sizeof(DevState));
+  offs[1] = o; o += up(sizeof(double) * kTraceCap * kTraceWidth);
+  offs[2] = o; o += up(sizeof(double) * (size_t)g.g.n_rb * (size_t)n);
+  offs[3] = o; o += up(sizeof(double) * (size_t)g.g.n_ct * (size_t)m);
+  offs[4] = o; o += up(sizeof(double) * (size_t)g.n_tiles * kTileSlots);
+  offs[5] = o; o += up(sizeof(double) * (size_t)m);
+  offs[6] = o; o += up(sizeof(double) * (size_t)n);
+  offs[7] = o; o += up(sizeof(double) * (size_t)m);
+  offs[8] = o; o += up(sizeof(double) * (size_t)n);
+  offs[9] = o; o += up(sizeof(double) * (size_t)m);
+  offs[10] = o; o += up(sizeof(double) * (size_t)n);
+  offs[11] = o; o += up(sizeof(double) * (size_t)(g.row_blocks + g.col_blocks) * kAuxSlots);
+  if (o <= c->ws_bytes) return DROT_OK;
+  drop_graph(c);
+  if (c->ws) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(c->ws);
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+  }
+  const size_t want = o + o / 4;  // headroom so that slightly larger problems reuse it
+  if (hipMalloc(&c->ws, want) != hipSuccess) {
+    (void)hipGetLastError();
+    c->ws = nullptr;
+    return fail(DROT_ENOMEM, "workspace allocation of %zu bytes failed", want);
+  }
+  c->ws_bytes = want;
+  return DROT_OK;
+}
+
+int launch_iteration(drot_ctx* c, hipStream_t s, hipEvent_t e0, hipEvent_t e1, bool capture) {
+  if (e0) {
+    hipError_t e = capture ? hipEventRecordWithFlags(e0, s, hipEventRecordExternal)
+                           : hipEventRecord(e0, s);
+    if (e != hipSuccess) return fail(DROT_EDEVICE, "event record: %s", hipGetErrorString(e));
+  }
+  HIP_TRY(launch_sweep(c->dtype, kIter, c->geo.vec, c->geo.chunks, c->sa, s));
+  if (e1) {
+    hipError_t e = capture ? hipEventRecordWithFlags(e1, s, hipEventRecordExternal)
+                           : hipEventRecord(e1, s);
+    if (e != hipSuccess) return fail(DROT_EDEVICE, "event record: %s", hipGetErrorString(e));
+  }
+  HIP_TRY(launch_aux(c->dtype, kIter, c->aa, s));
+  return DROT_OK;
+}
+
+int group_size(const drot_ctx* c) {
+  return c->prm.check_every > 0 ? c->prm.check_every : 32;
+}
+
+int ensure_events(drot_ctx* c, int count) {
+  while ((int)c->ev.size() < count) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    c->ev.push_back(e);
+  }
+  return DROT_OK;
+}
+
+int ensure_graph(drot_ctx* c) {
+  const int G = group_size(c);
+  const bool timed = (c->prm.flags & DROT_FLAG_TIME_SWEEP) != 0;
+  if (c->gexec && c->g_iters == G && c->g_timed == timed) return DROT_OK;
+  drop_graph(c);
+  if (timed) {
+    int rc = ensure_events(c, 2 * G);
+    if (rc) return rc;
+  }
+  HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  int rc = DROT_OK;
+  for (int k = 0; k < G && rc == DROT_OK; ++k)
+    rc = launch_iteration(c, c->cap_stream, timed ? c->ev[2 * k] : nullptr,
+                          timed ? c->ev[2 * k + 1] : nullptr, true);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+  if (rc != DROT_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(DROT_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    c->gexec = nullptr;
+    return fail(DROT_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
+  }
+  c->g_iters = G;
+  c->g_timed = timed;
+  return DROT_OK;
+}
+
+int harvest_events(drot_ctx* c, int pairs) {
+  for (int k = 0; k < pairs; ++k) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]));
+    c->sweep_ms += ms;
+    c->sweep_n += 1;
+  }
+  return DROT_OK;
+}
+
+int check_ctx(drot_ctx* c) {
+  if (!c) return fail(DROT_EINVAL, "ctx is NULL");
+  HIP_TRY(hipSetDevice(c->device));
+  return DROT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* drot_version(void) { return "drot-mi355x 0.1.0 (gfx950)"; }
+
+const char* drot_strerror(int s) {
+  switch (s) {
+    case DROT_OK: return "ok: stopping test met";
+    case DROT_MAXITER: return "max_iter reached before the stopping test";
+    case DROT_EINVAL: return "invalid argument";
+    case DROT_EMASS: return "marginals are negative or have unequal mass";
+    case DROT_ENONFINITE: return "non-finite value in the inputs or the iteration";
+    case DROT_ENOMEM: return "out of device memory";
+    case DROT_EDEVICE: return "no usable GPU or HIP runtime error";
+    case DROT_EUNSUPPORTED: return "unsupported combination";
+    case DROT_ESTATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+const char* drot_last_error(void) { return g_last_error.c_str(); }
+
+int drot_ctx_create(drot_ctx** out, int device) {
+  if (!out) return fail(DROT_EINVAL, "ctx output pointer is NULL");
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+    (void)hipGetLastError();
+    return fail(DROT_EDEVICE, "no HIP device available");
+  }
+  if (device < 0 || device >= count)
+    return fail(DROT_EINVAL, "device %d out of range [0, %d)", device, count);
+  HIP_TRY(hipSetDevice(device));
+  drot_ctx* c = new drot_ctx();
+  c->device = device;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
+    c->wall_rate = (double)khz * 1000.0;
+  if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipHostMalloc((void**)&c->st_host, sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    drot_ctx_destroy(c);
+    return fail(DROT_EDEVICE, "stream or pinned allocation failed");
+  }
+  memset(c->st_host, 0, sizeof(DevState));
+  *out = c;
+  return DROT_OK;
+}
+
+int drot_ctx_destroy(drot_ctx* c) {
+  if (!c) return DROT_OK;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  drop_graph(c);
+  for (auto e : c->ev) (void)hipEventDestroy(e);
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->st_host) (void)hipHostFree(c->st_host);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  delete c;
+  return DROT_OK;
+}
+
+int drot_bind(drot_ctx* c, int64_t m, int64_t n, int dtype, const void* C, int64_t ldc,
+              const void* p, const void* q, const drot_params* prm, void* X, int64_t ldx,
+              const double* mu0, const double* nu0, void* stream) {
+  int rc = validate(m, n, dtype, C, ldc, p, q, prm, X, ldx, mu0, nu0);
+  if (rc) return rc;
+  if ((rc = check_ctx(c))) return rc;
+  Geometry g;
+  if ((rc = choose_geometry(dtype, m, n, C, ldc, X, ldx, prm, &g))) return rc;
+  size_t offs[12];
+  if ((rc = ensure_workspace(c, m, n, g, offs))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  drop_graph(c);
+  c->bound = false;
+  c->finished = false;
+  c->dtype = dtype;
+  c->prm = *prm;
+  c->geo = g;
+  c->sweep_ms = 0.0;
+  c->sweep_n = 0;
+  char* base = static_cast<char*>(c->ws);
+  c->st = reinterpret_cast<DevState*>(base + offs[0]);
+  c->trace = reinterpret_cast<double*>(base + offs[1]);
+
+  SweepArgs& sa = c->sa;
+  sa = SweepArgs{};
+  sa.C = C;
+  sa.X = X;
+  sa.p = p;
+  sa.q = q;
+  sa.phiT = base + offs[9];
+  sa.psiT = base + offs[10];
+  sa.phi64 = reinterpret_cast<double*>(base + offs[7]);
+  sa.psi64 = reinterpret_cast<double*>(base + offs[8]);
+  sa.st = c->st;
+  sa.colpart = base + offs[2];
+  sa.rowpart = base + offs[3];
+  sa.tiles = reinterpret_cast<double*>(base + offs[4]);
+  sa.g = g.g;
+
+  AuxArgs& aa = c->aa;
+  aa = AuxArgs{};
+  aa.p = p;
+  aa.q = q;
+  aa.colpart = sa.colpart;
+  aa.rowpart = sa.rowpart;
+  aa.tiles = sa.tiles;
+  aa.a = reinterpret_cast<double*>(base + offs[5]);
+  aa.b = reinterpret_cast<double*>(base + offs[6]);
+  aa.phi64 = reinterpret_cast<double*>(base + offs[7]);
+  aa.psi64 = reinterpret_cast<double*>(base + offs[8]);
+  aa.phiT = base + offs[9];
+  aa.psiT = base + offs[10];
+  aa.mu0 = mu0;
+  aa.nu0 = nu0;
+  aa.blockpart = reinterpret_cast<double*>(base + offs[11]);
+  aa.trace = c->trace;
+  aa.st = c->st;
+  aa.m = m;
+  aa.n = n;
+  aa.n_ct = g.g.n_ct;
+  aa.n_rb = g.g.n_rb;
+  aa.n_tiles = g.n_tiles;
+  aa.row_blocks = g.row_blocks;
+  aa.col_blocks = g.col_blocks;
+  aa.wall_rate = c->wall_rate;
+
+  // Problem block of the device state.
+  DevState* h = c->st_host;
+  memset(h, 0, sizeof(DevState));
+  h->rho = prm->rho;
+  h->tol = prm->tol;
+  h->max_iter = prm->max_iter;
+  h->tol_mode = prm->tol_mode;
+  h->m = m;
+  h->n = n;
+  HIP_TRY(hipMemcpyAsync(c->st, h, sizeof(DevState), hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_prep(aa, s));
+  const int mode = prm->x0_mode == DROT_X0_GIVEN ? kInitX : kInitPQ;
+  HIP_TRY(launch_sweep(dtype, mode, g.vec, g.chunks, sa, s));
+  HIP_TRY(launch_aux(dtype, mode, aa, s));
+  HIP_TRY(hipMemcpyAsync(h, c->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+
+  if (h->init_bad > 0)
+    return fail(DROT_ENONFINITE,
+                "initialisation found %.0f non-finite entries in C, X_0, p, q or the warm "
+                "start, or negative entries in X_0",
+                h->init_bad);
+  if (h->init_neg > 0)
+    return fail(DROT_EMASS, "%.0f marginal entries are negative", h->init_neg);
+  const double eps = dtype == DROT_F32 ? 1.1920929e-07 : 2.220446049250313e-16;
+  const double sp = h->sum_p, sq = h->sum_q;
+  if (!(sp > 0) || std::fabs(sp - sq) > 8.0 * eps * std::max(sp, sq))
+    return fail(DROT_EMASS, "sum(p) = %.17g and sum(q) = %.17g differ (or are not positive)", sp, sq);
+  c->bound = true;
+  return DROT_OK;
+}
+
+int drot_iterate(drot_ctx* c, int64_t iters, void* stream) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!c->bound) return fail(DROT_ESTATE, "no problem bound (call drot_bind first)");
+  if (iters < 0) return fail(DROT_EINVAL, "iters must be >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  const bool timed = (c->prm.flags & DROT_FLAG_TIME_SWEEP) != 0;
+  const int G = group_size(c);
+  c->finished = false;
+  if (c->prm.flags & DROT_FLAG_NO_GRAPH) {
+    if (timed && (rc = ensure_events(c, 2 * G))) return rc;
+    int64_t done = 0;
+    while (done < iters) {
+      const int k = (int)std::min<int64_t>(G, iters - done);
+      for (int t = 0; t < k; ++t)
+        if ((rc = launch_iteration(c, s, timed ? c->ev[2 * t] : nullptr,
+                                   timed ? c->ev[2 * t + 1] : nullptr, false)))
+          return rc;
+      if (timed) {
+        HIP_TRY(hipStreamSynchronize(s));
+        if ((rc = harvest_events(c, k))) return rc;
+      }
+      done += k;
+    }
+    return DROT_OK;
+  }
+  if ((rc = ensure_graph(c))) return rc;
+  int64_t done = 0;
+  while (iters - done >= G) {
+    HIP_TRY(hipGraphLaunch(c->gexec, s));
+    if (timed) {
+      HIP_TRY(hipStreamSynchronize(s));
+      if ((rc = harvest_events(c, G))) return rc;
+    }
+    done += G;
+  }
+  // Remainder eagerly (its timing, if asked for, uses the leading event pairs).
+  const int rest = (int)(iters - done);
+  if (rest > 0) {
+    if (timed && (rc = ensure_events(c, 2 * rest))) return rc;
+    for (int t = 0; t < rest; ++t)
+      if ((rc = launch_iteration(c, s, timed ? c->ev[2 * t] : nullptr,
+                                 timed ? c->ev[2 * t + 1] : nullptr, false)))
+        return rc;
+    if (timed) {
+      HIP_TRY(hipStreamSynchronize(s));
+      if ((rc = harvest_events(c, rest))) return rc;
+    }
+  }
+  return DROT_OK;
+}
+
+int drot_poll(drot_ctx* c, int64_t* iters_done, int32_t* stopped, void* stream) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!c->bound) return fail(DROT_ESTATE, "no problem bound");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (iters_done) *iters_done = c->st_host->iter;
+  if (stopped) *stopped = c->st_host->done;
+  return DROT_OK;
+}
+
+int drot_finish(drot_ctx* c, double* mu, double* nu, drot_result* out, void* stream) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!c->bound) return fail(DROT_ESTATE, "no problem bound");
+  if (!out) return fail(DROT_EINVAL, "out is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  AuxArgs aa = c->aa;
+  aa.mu_out = mu;
+  aa.nu_out = nu;
+  HIP_TRY(launch_sweep(c->dtype, kFinal, c->geo.vec, c->geo.chunks, c->sa, s));
+  HIP_TRY(launch_aux(c->dtype, kFinal, aa, s));
+  HIP_TRY(hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const DevState* h = c->st_host;
+  memset(out, 0, sizeof(*out));
+  out->iters = h->iter;
+  out->status = h->done ? h->status : DROT_MAXITER;
+  out->objective = h->f_pobj;
+  out->dual_objective = h->f_dobj;
+  out->r_primal = h->f_rp;
+  out->r_dual = h->f_rd;
+  out->gap = h->f_gap;
+  out->eps_primal = h->f_eps_p;
+  out->eps_dual = h->f_eps_d;
+  out->eps_gap = h->f_eps_g;
+  const uint64_t t1 = h->done ? h->t_stop : h->t_last;
+  out->seconds_to_tol = (double)(t1 - h->t_start) / c->wall_rate;
+  out->sweep_ms_total = c->sweep_ms;
+  out->sweep_timed = c->sweep_n;
+  c->finished = true;
+  if (out->status == -3)
+    return fail(DROT_ENONFINITE, "the iteration produced a non-finite value at iteration %lld",
+                (long long)h->stop_iter);
+  return out->status;
+}
+
+int drot_get_trace(drot_ctx* c, int64_t first, int64_t count, double* host_out) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!c->bound) return fail(DROT_ESTATE, "no problem bound");
+  if (!host_out || count < 0) return fail(DROT_EINVAL, "bad output buffer or count");
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost));
+  const int64_t last = c->st_host->iter;
+  if (first < 1 || first + count - 1 > last || last - first >= kTraceCap)
+    return fail(DROT_EINVAL, "records [%lld, %lld] not available (have up to %lld, keep %d)",
+                (long long)first, (long long)(first + count - 1), (long long)last, kTraceCap);
+  for (int64_t k = first; k < first + count; ++k) {
+    const int64_t slot = (k - 1) % kTraceCap;
+    HIP_TRY(hipMemcpy(host_out + (k - first) * kTraceWidth, c->trace + slot * kTraceWidth,
+                      sizeof(double) * kTraceWidth, hipMemcpyDeviceToHost));
+  }
+  return DROT_OK;
+}
+
+int drot_solve(drot_ctx* c, int64_t m, int64_t n, int dtype, const void* C, int64_t ldc,
+               const void* p, const void* q, const drot_params* prm, void* X, int64_t ldx,
+               double* mu, double* nu, const double* mu0, const double* nu0, drot_result* out,
+               void* stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!out) return fail(DROT_EINVAL, "out is NULL");
+  int rc = validate(m, n, dtype, C, ldc, p, q, prm, X, ldx, mu0, nu0);
+  if (rc) return rc;
+  if ((rc = drot_bind(c, m, n, dtype, C, ldc, p, q, prm, X, ldx, mu0, nu0, stream))) return rc;
+  const int G = group_size(c);
+  int64_t done_iters = 0;
+  int32_t stopped = 0;
+  while (!stopped && done_iters < prm->max_iter) {
+    const int64_t k = std::min<int64_t>(G, prm->max_iter - done_iters);
+    if ((rc = drot_iterate(c, k, stream))) return rc;
+    if ((rc = drot_poll(c, &done_iters, &stopped, stream))) return rc;
+  }
+  rc = drot_finish(c, mu, nu, out, stream);
+  out->seconds_total =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return rc;
+}
+
+}  // extern "C"

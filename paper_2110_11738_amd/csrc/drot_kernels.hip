@@ -1,0 +1,630 @@
+// HIP kernels of the DROT hot path for gfx950 (CDNA4, wave64).
+//
+// One iteration of Algorithm 1 (DROT) is two launches:
+//   sweep : one fused pass over the dense m x n plan.  Each entry is read
+//           once (X and C) and written once (X):
+//             t     = phi_i + psi_j - rho c_ij
+//             x_ij <- max(x_ij + t, 0)                  (Algorithm 1, step 4)
+//           and in the same pass the row sums u = X e, the column sums
+//           v = X^T f (step 5), <C, X_{k+1}> and sum [t]_+^2, which is
+//           rho^2 r_dual^2 at the incoming shifts (Section 3, stopping
+//           criteria).  Reductions are two-level and run in a fixed order:
+//           per-tile partials (rowpart, colpart, tiles) are written here and
+//           summed by the aux kernel.  No floating-point atomics anywhere.
+//   aux   : the O(m+n) part (steps 5-8): level-2 sums u, v; r = u - p,
+//           s = v - q; the shift vectors without their common scalar part,
+//           phi~ = (a - 2r)/n, psi~ = (b - 2s)/m; a -= r, b -= s; block
+//           partials.  The last workgroup to finish reduces the block
+//           partials in a fixed order and does the scalar bookkeeping:
+//           beta = f^T r/(m+n), the scalar parts (2 beta - alpha)/n and
+//           (2 beta - alpha)/m of the new shifts, alpha -= beta, and the
+//           stopping test.
+// The split phi = phi~ + (2 beta - alpha)/n is the algebra of steps 6-7
+// written so that no second pass over the vectors is needed once beta is
+// known; the sweep adds the two scalar parts to the row shift.
+//
+// The paper's kernel (Section 3, "Main kernel") is column-major, assigns one
+// thread per row and combines column sums with float atomics.  Here X is
+// row-major, a wavefront's 64 lanes run along a row with 16-byte loads, each
+// lane keeps the column partials of its columns in registers over the tile's
+// rows, row sums use DPP cross-lane reductions, and every sum is
+// deterministic.
+#include "drot_internal.h"
+
+namespace drot {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Wave-level sum with DPP (all 64 lanes active).  The combination order is
+// fixed, so the result is bit-reproducible.  Result is valid in lane 63 and
+// broadcast through readlane.
+// ---------------------------------------------------------------------------
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xf, false);
+}
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp(float v) {
+  return __builtin_bit_cast(float, dpp_i<CTRL, ROW_MASK>(__builtin_bit_cast(int, v)));
+}
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp(double v) {
+  const unsigned long long bits = __builtin_bit_cast(unsigned long long, v);
+  const int lo = dpp_i<CTRL, ROW_MASK>((int)(unsigned)(bits & 0xffffffffull));
+  const int hi = dpp_i<CTRL, ROW_MASK>((int)(unsigned)(bits >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ float lane63(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
+__device__ __forceinline__ double lane63(double v) {
+  const unsigned long long bits = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)(bits & 0xffffffffull), 63);
+  const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(bits >> 32), 63);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+template <typename V>
+__device__ __forceinline__ V wave_sum(V v) {
+  v += dpp<0xB1>(v);         // quad_perm [1,0,3,2]: pairs
+  v += dpp<0x4E>(v);         // quad_perm [2,3,0,1]: quads
+  v += dpp<0x141>(v);        // row_half_mirror: groups of 8
+  v += dpp<0x140>(v);        // row_mirror: rows of 16
+  v += dpp<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+  return lane63(v);
+}
+
+// ---------------------------------------------------------------------------
+// Types.
+// ---------------------------------------------------------------------------
+template <typename T, int MODE>
+struct PartialOf {
+  using type = double;
+};
+template <>
+struct PartialOf<float, kIter> {
+  using type = float;
+};
+
+template <typename T, int VEC>
+struct VecOf;
+template <>
+struct VecOf<float, 4> {
+  typedef float type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct VecOf<double, 2> {
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+
+template <typename T, int VEC>
+__device__ __forceinline__ void load_chunk(const T* ptr, T (&out)[VEC]) {
+  if constexpr (VEC == 1) {
+    out[0] = *ptr;
+  } else {
+    using V = typename VecOf<T, VEC>::type;
+    const V v = *reinterpret_cast<const V*>(ptr);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) out[e] = v[e];
+  }
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void store_chunk(T* ptr, const T (&in)[VEC]) {
+  if constexpr (VEC == 1) {
+    *ptr = in[0];
+  } else {
+    using V = typename VecOf<T, VEC>::type;
+    V v;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) v[e] = in[e];
+    *reinterpret_cast<V*>(ptr) = v;
+  }
+}
+
+__device__ __forceinline__ bool finite_d(double v) { return __builtin_isfinite(v); }
+
+// ---------------------------------------------------------------------------
+// The fused sweep.  Tile = `rows` rows x W columns, W = 64 * VEC * CH.  The
+// four waves of a workgroup split the tile's rows into contiguous slices;
+// each lane owns CH chunks of VEC consecutive columns.
+// ---------------------------------------------------------------------------
+template <typename T, int MODE, int VEC, int CH>
+__global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a) {
+  using P = typename PartialOf<T, MODE>::type;
+  using A = typename std::conditional<MODE == kFinal, double, T>::type;
+  constexpr int CPL = VEC * CH;
+  constexpr int W = kWave * CPL;
+  constexpr int U = 4;
+
+  const DevState* st = a.st;
+  if (MODE == kIter && st->done) return;
+
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int ct = blockIdx.x % a.g.n_ct;
+  const int rb = blockIdx.x / a.g.n_ct;
+  const int64_t m = a.g.m, n = a.g.n;
+  const int64_t col0 = (int64_t)ct * W;
+  const int64_t row0 = (int64_t)rb * a.g.rows;
+  const int64_t rowE = row0 + a.g.rows < m ? row0 + a.g.rows : m;
+  const int rpw = (a.g.rows + kWaves - 1) / kWaves;
+  const int64_t rw0 = row0 + (int64_t)wave * rpw;
+  const int64_t rw1 = rw0 + rpw < rowE ? rw0 + rpw : rowE;
+
+  const T* __restrict__ C = static_cast<const T*>(a.C);
+  T* __restrict__ X = static_cast<T*>(a.X);
+
+  // Column layout of this lane: chunk c covers [jc[c], jc[c] + VEC).
+  int64_t jc[CH];
+  bool ok[CH];
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    jc[c] = col0 + (int64_t)c * kWave * VEC + (int64_t)lane * VEC;
+    ok[c] = jc[c] < n;  // the vector path is only used when n % VEC == 0
+  }
+
+  // Column shift of this lane's columns (or q_j for X_0 = p q^T).
+  A colv[CH][VEC];
+#pragma unroll
+  for (int c = 0; c < CH; ++c)
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      A v = 0;
+      if (ok[c]) {
+        const int64_t j = jc[c] + e;
+        if (MODE == kIter) v = static_cast<const T*>(a.psiT)[j];
+        if (MODE == kFinal) v = a.psi64[j];
+        if (MODE == kInitPQ) v = static_cast<const T*>(a.q)[j];
+      }
+      colv[c][e] = v;
+    }
+
+  A shift = 0, rho = 0;
+  if (MODE == kIter || MODE == kFinal) {
+    shift = (A)(st->cphi + st->cpsi);
+    rho = (A)st->rho;
+  }
+
+  P colacc[CH][VEC];
+#pragma unroll
+  for (int c = 0; c < CH; ++c)
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) colacc[c][e] = 0;
+  P s0 = 0, s1 = 0;  // tile scalars (cost & dual, or |C|^2 & bad count)
+
+  P* __restrict__ rowpart = static_cast<P*>(a.rowpart);
+
+  for (int64_t i0 = rw0; i0 < rw1; i0 += U) {
+    T xv[U][CH][VEC], cv[U][CH][VEC];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + u;
+      if (i < rw1) {
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+          if (ok[c]) {
+            load_chunk<T, VEC>(C + i * a.g.ldc + jc[c], cv[u][c]);
+            if (MODE != kInitPQ) load_chunk<T, VEC>(X + i * a.g.ldx + jc[c], xv[u][c]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + u;
+      if (i < rw1) {
+        A rowv = 0;
+        if (MODE == kIter) rowv = static_cast<const T*>(a.phiT)[i] + shift;
+        if (MODE == kFinal) rowv = a.phi64[i] + (double)shift;
+        if (MODE == kInitPQ) rowv = static_cast<const T*>(a.p)[i];
+        P rsum = 0;
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+          if (ok[c]) {
+            T outv[VEC];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+              const A cij = (A)cv[u][c][e];
+              A x;
+              if (MODE == kIter || MODE == kFinal) {
+                const A t = rowv + colv[c][e] - rho * cij;
+                const A tp = t > (A)0 ? t : (A)0;
+                s1 += (P)(tp * tp);
+                if (MODE == kIter) {
+                  const A y = (A)xv[u][c][e] + t;
+                  x = y > (A)0 ? y : (A)0;
+                } else {
+                  x = (A)xv[u][c][e];
+                }
+                s0 += (P)(cij * x);
+              } else {
+                if (MODE == kInitPQ) x = rowv * colv[c][e];
+                else x = (A)xv[u][c][e];
+                s0 += (P)((double)cij * (double)cij);
+                const bool bad = !finite_d((double)cij) || !finite_d((double)x) ||
+                                 (MODE == kInitX && x < (A)0);
+                s1 += bad ? (P)1 : (P)0;
+              }
+              outv[e] = (T)x;
+              rsum += (P)x;
+              colacc[c][e] += (P)x;
+            }
+            if (MODE == kIter || MODE == kInitPQ)
+              store_chunk<T, VEC>(X + i * a.g.ldx + jc[c], outv);
+          }
+        }
+        const P tot = wave_sum(rsum);
+        if (lane == 0) rowpart[(int64_t)ct * m + i] = tot;
+      }
+    }
+  }
+
+  // Column partials: combine the four waves' registers in LDS, fixed order.
+  __shared__ P sm[kWaves][W];
+  __shared__ double ssc[kWaves][2];
+#pragma unroll
+  for (int c = 0; c < CH; ++c)
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) sm[wave][c * kWave * VEC + lane * VEC + e] = colacc[c][e];
+  const P w0 = wave_sum(s0);
+  const P w1 = wave_sum(s1);
+  if (lane == 0) {
+    ssc[wave][0] = (double)w0;
+    ssc[wave][1] = (double)w1;
+  }
+  __syncthreads();
+  P* __restrict__ colpart = static_cast<P*>(a.colpart);
+  for (int k = threadIdx.x; k < W; k += kBlock) {
+    const int64_t j = col0 + k;
+    if (j < n) {
+      P v = sm[0][k];
+#pragma unroll
+      for (int w = 1; w < kWaves; ++w) v += sm[w][k];
+      colpart[(int64_t)rb * n + j] = v;
+    }
+  }
+  if (threadIdx.x == 0) {
+    double v0 = ssc[0][0], v1 = ssc[0][1];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) {
+      v0 += ssc[w][0];
+      v1 += ssc[w][1];
+    }
+    double* t = a.tiles + (int64_t)blockIdx.x * kTileSlots;
+    if (MODE == kIter || MODE == kFinal) {
+      t[kTsCost] = v0;
+      t[kTsDual] = v1;
+    } else {
+      t[kTsCsq] = v0;
+      t[kTsBad] = v1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Block-wide fixed-order sum of kAuxSlots values, result valid in thread 0.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void block_sum_slots(double (&acc)[kAuxSlots],
+                                                double (&red)[kAuxSlots][kAuxBlock / kWave]) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+#pragma unroll
+  for (int s = 0; s < kAuxSlots; ++s) {
+    const double v = wave_sum(acc[s]);
+    if (lane == 0) red[s][wave] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int s = 0; s < kAuxSlots; ++s) {
+      double v = red[s][0];
+      for (int w = 1; w < kAuxBlock / kWave; ++w) v += red[s][w];
+      acc[s] = v;
+    }
+  }
+}
+
+__device__ __forceinline__ void store_agent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_agent(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
+// The O(m+n) kernel.  Workgroups [0, row_blocks) own rows, the rest columns.
+// ---------------------------------------------------------------------------
+template <typename T, int MODE>
+__global__ __launch_bounds__(kAuxBlock) void aux_kernel(AuxArgs a) {
+  using P = typename PartialOf<T, MODE>::type;
+  DevState* st = a.st;
+  if (MODE == kIter && st->done) return;
+
+  __shared__ double red[kAuxSlots][kAuxBlock / kWave];
+  __shared__ int am_last;
+
+  double acc[kAuxSlots];
+#pragma unroll
+  for (int s = 0; s < kAuxSlots; ++s) acc[s] = 0.0;
+
+  const int b = blockIdx.x;
+  const int nb = gridDim.x;
+  const double rho = st->rho;
+  const int64_t m = a.m, n = a.n;
+
+  if (b < a.row_blocks) {
+    const int64_t i = (int64_t)b * kAuxBlock + threadIdx.x;
+    if (i < m) {
+      const P* rp = static_cast<const P*>(a.rowpart);
+      double u = 0.0;
+      for (int c = 0; c < a.n_ct; ++c) u += (double)rp[(int64_t)c * m + i];
+      const double pi = (double)static_cast<const T*>(a.p)[i];
+      const double r = u - pi;
+      if (MODE == kIter) {
+        const double ai = a.a[i];
+        const double ph = (ai - 2.0 * r) / (double)n;
+        a.a[i] = ai - r;
+        a.phi64[i] = ph;
+        static_cast<T*>(a.phiT)[i] = (T)ph;
+        acc[kAsR] = r;
+        acc[kAsR2] = r * r;
+        acc[kAsPphi] = pi * ph;
+      } else if (MODE == kFinal) {
+        const double ph = a.phi64[i] + st->cphi;
+        acc[kAsR2] = r * r;
+        acc[kAsPphi] = pi * ph;
+        if (a.mu_out) a.mu_out[i] = ph / rho;
+      } else {
+        const double ph0 = a.mu0 ? rho * a.mu0[i] : 0.0;
+        const double ai = u - pi + (double)n * ph0 + st->sum_psi0;
+        a.a[i] = ai;
+        a.phi64[i] = ph0;
+        static_cast<T*>(a.phiT)[i] = (T)ph0;
+        acc[kAsR] = ai;
+        acc[kAsP] = pi;
+        acc[kAsP2] = pi * pi;
+        acc[kAsNeg] = pi < 0.0 ? 1.0 : 0.0;
+        acc[kAsNonfin] = (!finite_d(pi) || !finite_d(ph0)) ? 1.0 : 0.0;
+      }
+    }
+  } else {
+    const int64_t j = (int64_t)(b - a.row_blocks) * kAuxBlock + threadIdx.x;
+    if (j < n) {
+      const P* cp = static_cast<const P*>(a.colpart);
+      double v = 0.0;
+      for (int r = 0; r < a.n_rb; ++r) v += (double)cp[(int64_t)r * n + j];
+      const double qj = (double)static_cast<const T*>(a.q)[j];
+      const double s = v - qj;
+      if (MODE == kIter) {
+        const double bj = a.b[j];
+        const double ps = (bj - 2.0 * s) / (double)m;
+        a.b[j] = bj - s;
+        a.psi64[j] = ps;
+        static_cast<T*>(a.psiT)[j] = (T)ps;
+        acc[kAsS] = s;
+        acc[kAsS2] = s * s;
+        acc[kAsQpsi] = qj * ps;
+      } else if (MODE == kFinal) {
+        const double ps = a.psi64[j] + st->cpsi;
+        acc[kAsS2] = s * s;
+        acc[kAsQpsi] = qj * ps;
+        if (a.nu_out) a.nu_out[j] = ps / rho;
+      } else {
+        const double ps0 = a.nu0 ? rho * a.nu0[j] : 0.0;
+        const double bj = v - qj + (double)m * ps0 + st->sum_phi0;
+        a.b[j] = bj;
+        a.psi64[j] = ps0;
+        static_cast<T*>(a.psiT)[j] = (T)ps0;
+        acc[kAsS] = bj;
+        acc[kAsQ] = qj;
+        acc[kAsP2] = qj * qj;
+        acc[kAsNeg] = qj < 0.0 ? 1.0 : 0.0;
+        acc[kAsNonfin] = (!finite_d(qj) || !finite_d(ps0)) ? 1.0 : 0.0;
+      }
+    }
+  }
+
+  // A fixed slice of the sweep's tile partials.
+  {
+    const int64_t t0 = (int64_t)a.n_tiles * b / nb;
+    const int64_t t1 = (int64_t)a.n_tiles * (b + 1) / nb;
+    const int sl0 = (MODE == kIter || MODE == kFinal) ? kTsCost : kTsCsq;
+    const int sl1 = (MODE == kIter || MODE == kFinal) ? kTsDual : kTsBad;
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += kAuxBlock) {
+      acc[kAsT0] += a.tiles[t * kTileSlots + sl0];
+      acc[kAsT1] += a.tiles[t * kTileSlots + sl1];
+    }
+  }
+
+  block_sum_slots(acc, red);
+  if (threadIdx.x == 0) {
+    for (int s = 0; s < kAuxSlots; ++s) store_agent(a.blockpart + (int64_t)b * kAuxSlots + s, acc[s]);
+    __threadfence();
+    const unsigned prev = atomicAdd(&st->counter, 1u);
+    am_last = (prev == (unsigned)(nb - 1));
+  }
+  __syncthreads();
+  if (!am_last) return;
+  __threadfence();
+
+  // Last workgroup: fixed-order reduction of the block partials.
+#pragma unroll
+  for (int s = 0; s < kAuxSlots; ++s) acc[s] = 0.0;
+  for (int k = threadIdx.x; k < nb; k += kAuxBlock)
+#pragma unroll
+    for (int s = 0; s < kAuxSlots; ++s) acc[s] += load_agent(a.blockpart + (int64_t)k * kAuxSlots + s);
+  __syncthreads();
+  block_sum_slots(acc, red);
+  if (threadIdx.x != 0) return;
+
+  const double mn = (double)(m + n);
+  const uint64_t now = wall_clock64();
+  if (MODE == kIter) {
+    const double beta = acc[kAsR] / mn;
+    const double alpha = st->alpha;
+    const double cc = 2.0 * beta - alpha;
+    const double cphi = cc / (double)n, cpsi = cc / (double)m;
+    const double pobj = acc[kAsT0];
+    const double dobj = (acc[kAsPphi] + cphi * st->sum_p + acc[kAsQpsi] + cpsi * st->sum_q) / rho;
+    const double gap = fabs(pobj - dobj);
+    const double rp = sqrt(acc[kAsR2] + acc[kAsS2]);
+    const double rd = sqrt(acc[kAsT1]) / rho;
+    const double ep = rp / fmax(st->norm_pq, 1e-300);
+    const double ed = rd / fmax(st->norm_c, 1e-300);
+    const double eg = gap / fmax(fmax(fabs(pobj), fabs(dobj)), 1e-300);
+    const double test = st->tol_mode ? fmax(rp, fmax(rd, gap)) : fmax(ep, fmax(ed, eg));
+    const int64_t k = st->iter + 1;
+    st->alpha = alpha - beta;
+    st->cphi = cphi;
+    st->cpsi = cpsi;
+    st->iter = k;
+    st->t_last = now;
+    st->pobj = pobj;
+    st->dobj = dobj;
+    st->rp = rp;
+    st->rd = rd;
+    st->gap = gap;
+    st->test = test;
+    double* tr = a.trace + ((k - 1) % kTraceCap) * kTraceWidth;
+    tr[0] = pobj;
+    tr[1] = dobj;
+    tr[2] = rp;
+    tr[3] = rd;
+    tr[4] = gap;
+    tr[5] = test;
+    tr[6] = (double)(now - st->t_start) / a.wall_rate;
+    tr[7] = (double)k;
+    int done = 0, status = 0;
+    if (!finite_d(test) || !finite_d(st->alpha) || !finite_d(cc)) {
+      done = 1;
+      status = -3;
+    } else if (test <= st->tol) {
+      done = 1;
+      status = 0;
+    } else if (k >= st->max_iter) {
+      done = 1;
+      status = 1;
+    }
+    if (done) {
+      st->done = 1;
+      st->status = status;
+      st->stop_iter = k;
+      st->t_stop = now;
+    }
+  } else if (MODE == kFinal) {
+    const double pobj = acc[kAsT0];
+    const double dobj = (acc[kAsPphi] + acc[kAsQpsi]) / rho;
+    st->f_pobj = pobj;
+    st->f_dobj = dobj;
+    st->f_rp = sqrt(acc[kAsR2] + acc[kAsS2]);
+    st->f_rd = sqrt(acc[kAsT1]) / rho;
+    st->f_gap = fabs(pobj - dobj);
+    st->f_eps_p = st->f_rp / fmax(st->norm_pq, 1e-300);
+    st->f_eps_d = st->f_rd / fmax(st->norm_c, 1e-300);
+    st->f_eps_g = st->f_gap / fmax(fmax(fabs(pobj), fabs(dobj)), 1e-300);
+  } else {
+    st->alpha = acc[kAsR] / mn;
+    st->sum_p = acc[kAsP];
+    st->sum_q = acc[kAsQ];
+    st->norm_pq = sqrt(acc[kAsP2]);
+    st->norm_c = sqrt(acc[kAsT0]);
+    st->init_bad = acc[kAsT1] + acc[kAsNonfin];
+    st->init_neg = acc[kAsNeg];
+    st->cphi = 0.0;
+    st->cpsi = 0.0;
+    st->iter = 0;
+    st->done = 0;
+    st->status = 0;
+    st->stop_iter = 0;
+  }
+  __hip_atomic_store(&st->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Warm-start sums sum(phi_0) = rho sum(mu0), sum(psi_0) = rho sum(nu0), and the
+// start timestamp.  One workgroup.
+__global__ __launch_bounds__(kAuxBlock) void prep_kernel(AuxArgs a) {
+  __shared__ double red[kAuxSlots][kAuxBlock / kWave];
+  double acc[kAuxSlots];
+#pragma unroll
+  for (int s = 0; s < kAuxSlots; ++s) acc[s] = 0.0;
+  if (a.mu0)
+    for (int64_t i = threadIdx.x; i < a.m; i += kAuxBlock) acc[0] += a.mu0[i];
+  if (a.nu0)
+    for (int64_t j = threadIdx.x; j < a.n; j += kAuxBlock) acc[1] += a.nu0[j];
+  block_sum_slots(acc, red);
+  if (threadIdx.x == 0) {
+    DevState* st = a.st;
+    st->sum_phi0 = st->rho * acc[0];
+    st->sum_psi0 = st->rho * acc[1];
+    st->t_start = wall_clock64();
+    st->t_stop = st->t_start;
+    st->t_last = st->t_start;
+    st->counter = 0;
+  }
+}
+
+template <typename T, int MODE, int VEC, int CH>
+hipError_t sweep_go(const SweepArgs& a, hipStream_t s) {
+  const int64_t tiles = (int64_t)a.g.n_ct * a.g.n_rb;
+  hipLaunchKernelGGL((sweep_kernel<T, MODE, VEC, CH>), dim3((unsigned)tiles), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T, int MODE>
+hipError_t sweep_mode(int vec, int chunks, const SweepArgs& a, hipStream_t s) {
+  constexpr int V = 16 / sizeof(T);
+  if (vec == V && chunks == 1) return sweep_go<T, MODE, V, 1>(a, s);
+  if (vec == V && chunks == 2) return sweep_go<T, MODE, V, 2>(a, s);
+  if (vec == 1 && chunks == 1) return sweep_go<T, MODE, 1, 1>(a, s);
+  if (vec == 1 && chunks == 4) return sweep_go<T, MODE, 1, 4>(a, s);
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t sweep_type(int mode, int vec, int chunks, const SweepArgs& a, hipStream_t s) {
+  switch (mode) {
+    case kIter: return sweep_mode<T, kIter>(vec, chunks, a, s);
+    case kInitPQ: return sweep_mode<T, kInitPQ>(vec, chunks, a, s);
+    case kInitX: return sweep_mode<T, kInitX>(vec, chunks, a, s);
+    case kFinal: return sweep_mode<T, kFinal>(vec, chunks, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t aux_type(int mode, const AuxArgs& a, hipStream_t s) {
+  const dim3 grid((unsigned)(a.row_blocks + a.col_blocks));
+  switch (mode) {
+    case kIter: hipLaunchKernelGGL((aux_kernel<T, kIter>), grid, dim3(kAuxBlock), 0, s, a); break;
+    case kInitPQ:
+    case kInitX: hipLaunchKernelGGL((aux_kernel<T, kInitPQ>), grid, dim3(kAuxBlock), 0, s, a); break;
+    case kFinal: hipLaunchKernelGGL((aux_kernel<T, kFinal>), grid, dim3(kAuxBlock), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_sweep(int dtype, int mode, int vec, int chunks, const SweepArgs& a,
+                        hipStream_t s) {
+  return dtype == 0 ? sweep_type<float>(mode, vec, chunks, a, s)
+                    : sweep_type<double>(mode, vec, chunks, a, s);
+}
+
+hipError_t launch_aux(int dtype, int mode, const AuxArgs& a, hipStream_t s) {
+  return dtype == 0 ? aux_type<float>(mode, a, s) : aux_type<double>(mode, a, s);
+}
+
+hipError_t launch_prep(const AuxArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(prep_kernel, dim3(1), dim3(kAuxBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace drot

@@ -1,0 +1,240 @@
+"""Python binding of libdrot.so (include/drot.h), argument marshalling only.
+
+Every step of the method runs in the library's HIP kernels; this module only
+passes pointers, sizes and the stream.  PyTorch supplies device memory and
+the current HIP stream.  If the library is missing the import of this module
+still works, but every call raises: there is no CPU fallback.
+
+    from paper_2110_11738_amd import drot
+    X, res, mu, nu = drot.solve(C, p, q, rho, tol)      # C, p, q: cuda tensors
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libdrot.so")
+
+OK, MAXITER = 0, 1
+EINVAL, EMASS, ENONFINITE, ENOMEM, EDEVICE, EUNSUPPORTED, ESTATE = -1, -2, -3, -4, -5, -6, -7
+F32, F64 = 0, 1
+TOL_RELATIVE, TOL_ABSOLUTE = 0, 1
+X0_PQ, X0_GIVEN = 0, 1
+FLAG_NO_GRAPH, FLAG_TIME_SWEEP = 0x1, 0x2
+TRACE_FIELDS = ("pobj", "dobj", "r_primal", "r_dual_lag", "gap", "test", "seconds", "k")
+
+EXPORTED = ("drot_version", "drot_strerror", "drot_last_error", "drot_ctx_create",
+            "drot_ctx_destroy", "drot_solve", "drot_bind", "drot_iterate", "drot_poll",
+            "drot_finish", "drot_get_trace")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("rho", ctypes.c_double), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int64), ("tol_mode", ctypes.c_int32),
+                ("x0_mode", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
+                ("tile_chunks", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int64), ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("objective", ctypes.c_double),
+                ("dual_objective", ctypes.c_double), ("r_primal", ctypes.c_double),
+                ("r_dual", ctypes.c_double), ("gap", ctypes.c_double),
+                ("eps_primal", ctypes.c_double), ("eps_dual", ctypes.c_double),
+                ("eps_gap", ctypes.c_double), ("seconds_to_tol", ctypes.c_double),
+                ("seconds_total", ctypes.c_double), ("sweep_ms_total", ctypes.c_double),
+                ("sweep_timed", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class DrotError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libdrot.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2110_11738_amd.build` (no CPU fallback exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    L.drot_version.restype = ctypes.c_char_p
+    L.drot_strerror.restype = ctypes.c_char_p
+    L.drot_strerror.argtypes = [i32]
+    L.drot_last_error.restype = ctypes.c_char_p
+    L.drot_ctx_create.argtypes = [ctypes.POINTER(vp), i32]
+    L.drot_ctx_destroy.argtypes = [vp]
+    common = [vp, i64, i64, i32, vp, i64, vp, vp, ctypes.POINTER(Params), vp, i64]
+    L.drot_solve.argtypes = common + [vp, vp, vp, vp, ctypes.POINTER(Result), vp]
+    L.drot_bind.argtypes = common + [vp, vp, vp]
+    L.drot_iterate.argtypes = [vp, i64, vp]
+    L.drot_poll.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int32), vp]
+    L.drot_finish.argtypes = [vp, vp, vp, ctypes.POINTER(Result), vp]
+    L.drot_get_trace.argtypes = [vp, i64, i64, ctypes.POINTER(ctypes.c_double)]
+    for name in EXPORTED:
+        getattr(L, name).restype = getattr(L, name).restype or i32
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().drot_last_error().decode()
+
+
+def _check(rc: int, allow=(OK, MAXITER)) -> int:
+    if rc not in allow:
+        raise DrotError(rc, f"{lib().drot_strerror(rc).decode()}: {last_error()}")
+    return rc
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise TypeError(f"unsupported dtype {t.dtype} (float32 or float64)")
+
+
+def _ld(t) -> int:
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("matrices must be 2-D with unit column stride (row-major)")
+    return t.stride(0)
+
+
+def make_params(rho, tol=0.0, max_iter=100000, tol_mode=TOL_RELATIVE, x0_mode=X0_PQ,
+                check_every=0, flags=0, tile_rows=0, tile_chunks=0) -> Params:
+    return Params(float(rho), float(tol), int(max_iter), int(tol_mode), int(x0_mode),
+                  int(check_every), int(flags), int(tile_rows), int(tile_chunks))
+
+
+class Context:
+    """Owns a drot_ctx (workspace, graphs) on one device."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().drot_ctx_create(ctypes.byref(h), int(device)), allow=(OK,))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().drot_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- step-wise interface --------------------------------------------
+    def bind(self, C, p, q, X, params: Params, mu0=None, nu0=None, stream=None):
+        self._keep = (C, p, q, X, mu0, nu0)   # the library holds these pointers
+        m, n = C.shape
+        rc = lib().drot_bind(self.handle, m, n, _dtype_code(C), _ptr(C), _ld(C), _ptr(p),
+                             _ptr(q), ctypes.byref(params), _ptr(X), _ld(X), _ptr(mu0),
+                             _ptr(nu0), _stream(stream))
+        return _check(rc, allow=(OK,))
+
+    def iterate(self, iters: int, stream=None):
+        return _check(lib().drot_iterate(self.handle, int(iters), _stream(stream)), allow=(OK,))
+
+    def poll(self, stream=None):
+        k = ctypes.c_int64()
+        s = ctypes.c_int32()
+        _check(lib().drot_poll(self.handle, ctypes.byref(k), ctypes.byref(s), _stream(stream)),
+               allow=(OK,))
+        return k.value, bool(s.value)
+
+    def finish(self, mu=None, nu=None, stream=None) -> dict:
+        r = Result()
+        rc = lib().drot_finish(self.handle, _ptr(mu), _ptr(nu), ctypes.byref(r), _stream(stream))
+        _check(rc)
+        return r.as_dict()
+
+    def trace(self, first: int, count: int):
+        import numpy as np
+        out = np.zeros((count, 8), dtype=np.float64)
+        rc = lib().drot_get_trace(self.handle, int(first), int(count),
+                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        _check(rc, allow=(OK,))
+        return out
+
+    # -- one-call solve ----------------------------------------------------
+    def solve(self, C, p, q, params: Params, X=None, mu=None, nu=None, mu0=None, nu0=None,
+              stream=None):
+        import torch
+        m, n = C.shape
+        if X is None:
+            X = torch.empty((m, n), dtype=C.dtype, device=C.device)
+        r = Result()
+        rc = lib().drot_solve(self.handle, m, n, _dtype_code(C), _ptr(C), _ld(C), _ptr(p),
+                              _ptr(q), ctypes.byref(params), _ptr(X), _ld(X), _ptr(mu),
+                              _ptr(nu), _ptr(mu0), _ptr(nu0), ctypes.byref(r), _stream(stream))
+        _check(rc)
+        return X, r.as_dict()
+
+
+_default_ctx: dict = {}
+
+
+def default_context(device: int = 0) -> Context:
+    if device not in _default_ctx:
+        _default_ctx[device] = Context(device)
+    return _default_ctx[device]
+
+
+@dataclass
+class Solution:
+    X: object
+    mu: object
+    nu: object
+    result: dict
+
+
+def solve(C, p, q, rho: float, tol: float = 1e-4, max_iter: int = 100000,
+          tol_mode: int = TOL_RELATIVE, X0=None, mu0=None, nu0=None, check_every: int = 0,
+          flags: int = 0, tile_rows: int = 0, tile_chunks: int = 0, ctx: Context | None = None,
+          stream=None):
+    """solve(C, p, q, rho, tol) -> (X, result, mu, nu) on C's device.
+
+    C (m x n), p (m), q (n): float32 or float64 CUDA tensors.  X0 (optional)
+    is the starting plan (default p q^T).  mu0/nu0 (optional, float64) warm
+    start the dual shifts.  Returns the plan X_K, the result record (status,
+    iterations, objective, residuals, timings) and mu, nu (float64)."""
+    import torch
+    if not (C.is_cuda and p.is_cuda and q.is_cuda):
+        raise ValueError("C, p and q must be device tensors")
+    ctx = ctx or default_context(C.device.index or 0)
+    m, n = C.shape
+    X = torch.empty((m, n), dtype=C.dtype, device=C.device) if X0 is None else X0
+    mu = torch.empty(m, dtype=torch.float64, device=C.device)
+    nu = torch.empty(n, dtype=torch.float64, device=C.device)
+    prm = make_params(rho, tol, max_iter, tol_mode, X0_PQ if X0 is None else X0_GIVEN,
+                      check_every, flags, tile_rows, tile_chunks)
+    X, res = ctx.solve(C, p, q, prm, X=X, mu=mu, nu=nu, mu0=mu0, nu0=nu0, stream=stream)
+    return X, res, mu, nu

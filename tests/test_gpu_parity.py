@@ -1,0 +1,247 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Both sides solve the same seeded instance; for float32 runs the oracle gets
+the float32-rounded data upcast exactly to float64.  Trajectory parity runs
+the same K iterations from X_0 = p q^T on both sides and compares X_K, the
+dual variables and the per-iteration stopping-test quantities element by
+element.  Tolerances: float64 1e-10 relative to the largest entry (only the
+summation order differs); float32 rounding of the stored plan and partial
+sums, derived in the design notes, is bounded by the float32 tolerances below.
+"""
+import numpy as np
+import pytest
+
+from gen import (assignment_instance, config_mixture_2d, config_small_fp64, round_to)
+from oracle import certify, exact, ref
+
+pytestmark = pytest.mark.gpu
+
+TOL = {  # (X rel-to-max, dual rel-to-max, objective rel)
+    "float64": (1e-10, 1e-9, 1e-10),
+    "float32": (2e-5, 5e-3, 2e-5),
+}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2110_11738_amd import drot
+    c = drot.Context(0)
+    yield c
+    c.close()
+
+
+def _upload(inst, dtype):
+    torch = _torch()
+    dt = torch.float32 if dtype == "float32" else torch.float64
+    dev = torch.device("cuda:0")
+    C = torch.tensor(inst.C, dtype=dt, device=dev)
+    p = torch.tensor(inst.p, dtype=dt, device=dev)
+    q = torch.tensor(inst.q, dtype=dt, device=dev)
+    return C, p, q
+
+
+def _rounded(inst, dtype):
+    return round_to(inst, np.float32) if dtype == "float32" else inst
+
+
+def _run(ctx, inst, dtype, K, tol=0.0, **kw):
+    from paper_2110_11738_amd import drot
+    C, p, q = _upload(inst, dtype)
+    X, res, mu, nu = drot.solve(C, p, q, inst.rho, tol=tol, max_iter=K, ctx=ctx, **kw)
+    _torch().cuda.synchronize()
+    return (X.double().cpu().numpy(), res, mu.cpu().numpy(), nu.cpu().numpy())
+
+
+def _rel_max(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+SHAPES = [(1, 1), (1, 7), (9, 1), (3, 5), (37, 129), (300, 260), (513, 1030), (64, 2048)]
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("m,n", SHAPES, ids=lambda v: str(v))
+def test_trajectory_parity(ctx, dtype, m, n):
+    inst = _rounded(config_mixture_2d(7, m, n), dtype)
+    for K in (1, 3, 25):
+        print(f"[trajectory] {dtype} {m}x{n} K={K}", flush=True)
+        Xg, res, mu, nu = _run(ctx, inst, dtype, K)
+        R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=K, trace=True)
+        tx, td, to = TOL[dtype]
+        assert res["iters"] == K
+        ex = _rel_max(Xg, R.X)
+        emu = _rel_max(mu, R.mu)
+        enu = _rel_max(nu, R.nu)
+        eobj = abs(res["objective"] - R.info["pobj"]) / max(abs(R.info["pobj"]), 1e-300)
+        print(f"    X {ex:.2e} mu {emu:.2e} nu {enu:.2e} obj {eobj:.2e}", flush=True)
+        assert Xg.min() >= 0.0
+        assert ex <= tx
+        assert emu <= td and enu <= td
+        assert eobj <= to
+        # final-evaluation residuals against the oracle's exact evaluation; a
+        # float32 plan cannot meet its marginals closer than the rounding of
+        # its entries (about 2^-24 of each row and column sum).
+        ev = ref.evaluate(inst.C, inst.p, inst.q, inst.rho, R.X, R.phi, R.psi)
+        floor = (16 * 2.0 ** -24 if dtype == "float32" else 1e-13) * ev["norm_pq"]
+        assert abs(res["r_primal"] - ev["r_primal"]) <= 1e-3 * ev["r_primal"] + floor
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_trace_matches_oracle(ctx, dtype):
+    inst = _rounded(config_mixture_2d(8, 200, 333), dtype)
+    K = 40
+    C, p, q = _upload(inst, dtype)
+    from paper_2110_11738_amd import drot
+    drot.solve(C, p, q, inst.rho, tol=0.0, max_iter=K, ctx=ctx)
+    tr = ctx.trace(1, K)
+    R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=K, trace=True)
+    rel = 1e-9 if dtype == "float64" else 1e-3
+    np.testing.assert_array_equal(tr[:, 7], np.arange(1, K + 1))
+    for col, name in enumerate(["pobj", "dobj", "r_primal", "r_dual_lag", "gap"]):
+        a, b = tr[:, col], R.trace[:, col]
+        scale = np.abs(b).max() + 1e-300
+        err = np.abs(a - b).max() / scale
+        print(f"[trace] {dtype} {name}: {err:.2e}", flush=True)
+        assert err <= rel, name
+
+
+def test_solve_small_fp64_matches_oracle_and_lp(ctx):
+    inst = config_small_fp64(0)
+    print("[solve] small fp64 100x100 tol 1e-6", flush=True)
+    Xg, res, mu, nu = _run(ctx, inst, "float64", 2_000_000, tol=inst.tol)
+    R = ref.solve_instance(inst, max_iter=2_000_000)
+    opt = exact.lp_highs(inst.C, inst.p, inst.q)[0]
+    print(f"    gpu iters {res['iters']} oracle {R.info['iters']} obj {res['objective']:.12e} "
+          f"oracle {R.info['pobj']:.12e} opt {opt:.12e}", flush=True)
+    assert res["status"] == 0
+    assert abs(res["iters"] - R.info["iters"]) <= 1
+    assert abs(res["objective"] - R.info["pobj"]) / R.info["pobj"] <= 1e-6
+    assert abs(res["objective"] - opt) / opt <= 5e-6
+    assert res["eps_primal"] <= 1e-6
+
+
+@pytest.mark.parametrize("n", [4, 7, 64])
+def test_assignment_pin(ctx, n):
+    inst = assignment_instance(1, n)
+    opt = exact.assignment_uniform(inst.C)
+    Xg, res, mu, nu = _run(ctx, inst, "float64", 2_000_000, tol=1e-9)
+    print(f"[assignment] n={n} obj {res['objective']:.12e} opt {opt:.12e}", flush=True)
+    assert res["status"] == 0
+    assert abs(res["objective"] - opt) <= 1e-7 * max(opt, 1e-3)
+
+
+def test_solve_fp32_mixture_matches_oracle(ctx):
+    inst = round_to(config_mixture_2d(2, 256, 320), np.float32)
+    print("[solve] fp32 mixture 256x320 tol 1e-4", flush=True)
+    Xg, res, mu, nu = _run(ctx, inst, "float32", 1_000_000, tol=1e-4)
+    R = ref.solve_instance(inst, max_iter=1_000_000)
+    print(f"    gpu iters {res['iters']} oracle {R.info['iters']} obj {res['objective']:.10e} "
+          f"oracle {R.info['pobj']:.10e}", flush=True)
+    assert res["status"] == 0
+    assert abs(res["objective"] - R.info["pobj"]) / R.info["pobj"] <= 1e-4
+    assert res["eps_primal"] <= 1e-4
+    assert Xg.min() >= 0
+    lb, ub = certify.bracket(inst.C, inst.p, inst.q, Xg, mu)
+    assert lb <= res["objective"] * (1 + 1e-4) and res["objective"] <= ub * (1 + 1e-4)
+
+
+@pytest.mark.parametrize("dtype", ["float32", "float64"])
+def test_deterministic(ctx, dtype):
+    inst = _rounded(config_mixture_2d(3, 700, 900), dtype)
+    a = _run(ctx, inst, dtype, 60)
+    b = _run(ctx, inst, dtype, 60)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[2], b[2])
+    np.testing.assert_array_equal(a[3], b[3])
+    assert a[1]["objective"] == b[1]["objective"]
+
+
+@pytest.mark.parametrize("dtype", ["float32", "float64"])
+def test_graph_and_eager_agree(ctx, dtype):
+    from paper_2110_11738_amd import drot
+    inst = _rounded(config_mixture_2d(4, 333, 444), dtype)
+    a = _run(ctx, inst, dtype, 70, check_every=16)
+    b = _run(ctx, inst, dtype, 70, flags=drot.FLAG_NO_GRAPH)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("tile_rows,tile_chunks", [(16, 1), (64, 2), (256, 1), (0, 0)])
+def test_tile_shapes_agree_with_oracle(ctx, tile_rows, tile_chunks):
+    inst = round_to(config_mixture_2d(5, 1000, 1536), np.float32)
+    Xg, res, mu, nu = _run(ctx, inst, "float32", 10, tile_rows=tile_rows, tile_chunks=tile_chunks)
+    R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=10)
+    assert _rel_max(Xg, R.X) <= TOL["float32"][0]
+
+
+def test_padded_leading_dimension_and_scalar_path(ctx):
+    """ldx > n with a ragged n (scalar path): padding columns stay untouched."""
+    torch = _torch()
+    from paper_2110_11738_amd import drot
+    inst = round_to(config_mixture_2d(6, 130, 203), np.float32)
+    C, p, q = _upload(inst, "float32")
+    Cpad = torch.full((130, 211), 7.0, dtype=torch.float32, device="cuda")[:, :203]
+    Cpad.copy_(C)
+    Xbig = torch.full((130, 210), -3.0, dtype=torch.float32, device="cuda")
+    X = Xbig[:, :203]
+    prm = drot.make_params(inst.rho, 0.0, 20)
+    X, res = ctx.solve(Cpad, p, q, prm, X=X)
+    torch.cuda.synchronize()
+    R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=20)
+    assert _rel_max(X.double().cpu().numpy(), R.X) <= TOL["float32"][0]
+    assert torch.all(Xbig[:, 203:] == -3.0)
+
+
+def test_warm_start_and_given_x0(ctx):
+    torch = _torch()
+    from paper_2110_11738_amd import drot
+    inst = config_small_fp64(9, 40, 56)
+    rng = np.random.default_rng(3)
+    mu0 = 0.05 * rng.standard_normal(40)
+    nu0 = 0.05 * rng.standard_normal(56)
+    X0 = rng.uniform(0, 2.0 / (40 * 56), (40, 56))
+    C, p, q = _upload(inst, "float64")
+    Xg, res, mu, nu = drot.solve(C, p, q, inst.rho, tol=0.0, max_iter=30, ctx=ctx,
+                                 X0=torch.tensor(X0, device="cuda"),
+                                 mu0=torch.tensor(mu0, device="cuda"),
+                                 nu0=torch.tensor(nu0, device="cuda"))
+    R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=30, X0=X0,
+                  phi0=inst.rho * mu0, psi0=inst.rho * nu0)
+    assert _rel_max(Xg.cpu().numpy(), R.X) <= 1e-10
+    assert _rel_max(mu.cpu().numpy(), R.mu) <= 1e-9
+
+
+def test_error_paths(ctx):
+    torch = _torch()
+    from paper_2110_11738_amd import drot
+    inst = config_small_fp64(0, 20, 30)
+    C, p, q = _upload(inst, "float64")
+    # unequal mass
+    with pytest.raises(drot.DrotError) as e:
+        drot.solve(C, p, q * 1.01, inst.rho, ctx=ctx)
+    assert e.value.code == drot.EMASS
+    # negative marginal entry
+    p2 = p.clone()
+    p2[0] = -p2[0]
+    with pytest.raises(drot.DrotError) as e:
+        drot.solve(C, p2, q, inst.rho, ctx=ctx)
+    assert e.value.code == drot.EMASS
+    # NaN in C
+    C2 = C.clone()
+    C2[3, 4] = float("nan")
+    with pytest.raises(drot.DrotError) as e:
+        drot.solve(C2, p, q, inst.rho, ctx=ctx)
+    assert e.value.code == drot.ENONFINITE
+    # bad parameters are caught before any launch
+    with pytest.raises(drot.DrotError) as e:
+        drot.solve(C, p, q, -1.0, ctx=ctx)
+    assert e.value.code == drot.EINVAL
+    # max_iter status is not an error
+    X, res, mu, nu = drot.solve(C, p, q, inst.rho, tol=1e-12, max_iter=5, ctx=ctx)
+    assert res["status"] == drot.MAXITER and res["iters"] == 5
+    torch.cuda.synchronize()
