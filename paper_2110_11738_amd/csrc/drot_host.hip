@@ -48,7 +48,6 @@ struct Geometry {
   int vec = 1, chunks = 1;
   SweepGeom g{};
   int n_tiles = 0;
-  int row_blocks = 0, col_blocks = 0;
 };
 
 }  // namespace
@@ -71,7 +70,6 @@ struct drot_ctx {
   drot_params prm{};
   Geometry geo;
   SweepArgs sa{};
-  AuxArgs aa{};
   bool finished = false;
 
   // Graph of `check_every` iterations.
@@ -128,9 +126,8 @@ int choose_geometry(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc,
   g.g.n_ct = (int)n_ct;
   g.g.n_rb = (int)n_rb;
   g.g.rows = rows;
+  g.g.ldcp = n_ct * W;
   g.n_tiles = (int)(n_ct * n_rb);
-  g.row_blocks = (int)((m + kAuxBlock - 1) / kAuxBlock);
-  g.col_blocks = (int)((n + kAuxBlock - 1) / kAuxBlock);
   *out = g;
   return DROT_OK;
 }
@@ -169,20 +166,26 @@ int validate(int64_t m, int64_t n, int dtype, const void* C, int64_t ldc, const 
 }
 
 int ensure_workspace(drot_ctx* c, int64_t m, int64_t n, const Geometry& g, size_t* offs) {
-  // offsets: st, trace, colpart, rowpart, tiles, a, b, phi64, psi64, phiT, psiT, blockpart
+  // st, trace, colpart, rowpart, tiles, a, b, phi64, psi64, phiT, psiT,
+  // blockpart
   size_t o = 0;
-  offs[0] = o; o += up(sizeof(DevState));
-  offs[1] = o; o += up(sizeof(double) * kTraceCap * kTraceWidth);
-  offs[2] = o; o += up(sizeof(double) * (size_t)g.g.n_rb * (size_t)n);
-  offs[3] = o; o += up(sizeof(double) * (size_t)g.g.n_ct * (size_t)m);
-  offs[4] = o; o += up(sizeof(double) * (size_t)g.n_tiles * kTileSlots);
-  offs[5] = o; o += up(sizeof(double) * (size_t)m);
-  offs[6] = o; o += up(sizeof(double) * (size_t)n);
-  offs[7] = o; o += up(sizeof(double) * (size_t)m);
-  offs[8] = o; o += up(sizeof(double) * (size_t)n);
-  offs[9] = o; o += up(sizeof(double) * (size_t)m);
-  offs[10] = o; o += up(sizeof(double) * (size_t)n);
-  offs[11] = o; o += up(sizeof(double) * (size_t)(g.row_blocks + g.col_blocks) * kAuxSlots);
+  const size_t sizes[12] = {
+      sizeof(DevState),
+      sizeof(double) * kTraceCap * kTraceWidth,
+      sizeof(double) * (size_t)g.g.n_rb * (size_t)g.g.ldcp,
+      sizeof(double) * (size_t)g.g.n_ct * (size_t)m,
+      sizeof(double) * (size_t)g.n_tiles * kTileSlots,
+      sizeof(double) * (size_t)m,
+      sizeof(double) * (size_t)n,
+      sizeof(double) * (size_t)m,
+      sizeof(double) * (size_t)n,
+      sizeof(double) * (size_t)m,
+      sizeof(double) * (size_t)n,
+      sizeof(double) * (size_t)aux_workgroups(m, n) * kSlots};
+  for (int k = 0; k < 12; ++k) {
+    offs[k] = o;
+    o += up(sizes[k]);
+  }
   if (o <= c->ws_bytes) return DROT_OK;
   drop_graph(c);
   if (c->ws) {
@@ -201,19 +204,11 @@ int ensure_workspace(drot_ctx* c, int64_t m, int64_t n, const Geometry& g, size_
   return DROT_OK;
 }
 
-int launch_iteration(drot_ctx* c, hipStream_t s, hipEvent_t e0, hipEvent_t e1, bool capture) {
-  if (e0) {
-    hipError_t e = capture ? hipEventRecordWithFlags(e0, s, hipEventRecordExternal)
-                           : hipEventRecord(e0, s);
-    if (e != hipSuccess) return fail(DROT_EDEVICE, "event record: %s", hipGetErrorString(e));
-  }
+int launch_iteration(drot_ctx* c, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (e0) HIP_TRY(hipEventRecord(e0, s));
   HIP_TRY(launch_sweep(c->dtype, kIter, c->geo.vec, c->geo.chunks, c->sa, s));
-  if (e1) {
-    hipError_t e = capture ? hipEventRecordWithFlags(e1, s, hipEventRecordExternal)
-                           : hipEventRecord(e1, s);
-    if (e != hipSuccess) return fail(DROT_EDEVICE, "event record: %s", hipGetErrorString(e));
-  }
-  HIP_TRY(launch_aux(c->dtype, kIter, c->aa, s));
+  if (e1) HIP_TRY(hipEventRecord(e1, s));
+  HIP_TRY(launch_aux(c->dtype, kIter, c->sa, s));
   return DROT_OK;
 }
 
@@ -230,28 +225,74 @@ int ensure_events(drot_ctx* c, int count) {
   return DROT_OK;
 }
 
+// Capture one launch (the sweep or the aux kernel) into a one-node graph.
+int capture_one(drot_ctx* c, bool sweep, hipGraph_t* out) {
+  HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = sweep ? launch_sweep(c->dtype, kIter, c->geo.vec, c->geo.chunks, c->sa, c->cap_stream)
+                       : launch_aux(c->dtype, kIter, c->sa, c->cap_stream);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(DROT_EDEVICE, "capture: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  *out = g;
+  return DROT_OK;
+}
+
+// Graph of G iterations with an event-record node before and after every
+// sweep (DROT_FLAG_TIME_SWEEP), built node by node; the kernels enter as
+// captured child graphs.
+int build_timed_graph(drot_ctx* c, int G, hipGraph_t* out) {
+  hipGraph_t gs = nullptr, ga = nullptr, g = nullptr;
+  int rc = capture_one(c, true, &gs);
+  if (!rc) rc = capture_one(c, false, &ga);
+  hipError_t e = hipSuccess;
+  if (!rc) e = hipGraphCreate(&g, 0);
+  hipGraphNode_t prev = nullptr;
+  for (int k = 0; k < G && !rc && e == hipSuccess; ++k) {
+    hipGraphNode_t e0, s, e1, x;
+    e = hipGraphAddEventRecordNode(&e0, g, prev ? &prev : nullptr, prev ? 1 : 0, c->ev[2 * k]);
+    if (e == hipSuccess) e = hipGraphAddChildGraphNode(&s, g, &e0, 1, gs);
+    if (e == hipSuccess) e = hipGraphAddEventRecordNode(&e1, g, &s, 1, c->ev[2 * k + 1]);
+    if (e == hipSuccess) e = hipGraphAddChildGraphNode(&x, g, &e1, 1, ga);
+    prev = x;
+  }
+  if (gs) (void)hipGraphDestroy(gs);
+  if (ga) (void)hipGraphDestroy(ga);
+  if (!rc && e != hipSuccess) rc = fail(DROT_EDEVICE, "timed graph: %s", hipGetErrorString(e));
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return rc;
+  }
+  *out = g;
+  return DROT_OK;
+}
+
 int ensure_graph(drot_ctx* c) {
   const int G = group_size(c);
   const bool timed = (c->prm.flags & DROT_FLAG_TIME_SWEEP) != 0;
   if (c->gexec && c->g_iters == G && c->g_timed == timed) return DROT_OK;
   drop_graph(c);
+  hipGraph_t graph = nullptr;
   if (timed) {
     int rc = ensure_events(c, 2 * G);
     if (rc) return rc;
+    if ((rc = build_timed_graph(c, G, &graph))) return rc;
+  } else {
+    HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = DROT_OK;
+    for (int k = 0; k < G && rc == DROT_OK; ++k)
+      rc = launch_iteration(c, c->cap_stream, nullptr, nullptr);
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+    if (rc != DROT_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(DROT_EDEVICE, "graph capture: %s", hipGetErrorString(e));
   }
-  HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-  int rc = DROT_OK;
-  for (int k = 0; k < G && rc == DROT_OK; ++k)
-    rc = launch_iteration(c, c->cap_stream, timed ? c->ev[2 * k] : nullptr,
-                          timed ? c->ev[2 * k + 1] : nullptr, true);
-  hipGraph_t graph = nullptr;
-  hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
-  if (rc != DROT_OK) {
-    if (graph) (void)hipGraphDestroy(graph);
-    return rc;
-  }
-  if (e != hipSuccess) return fail(DROT_EDEVICE, "graph capture: %s", hipGetErrorString(e));
-  e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+  hipError_t e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) {
     c->gexec = nullptr;
@@ -370,42 +411,22 @@ int drot_bind(drot_ctx* c, int64_t m, int64_t n, int dtype, const void* C, int64
   sa.X = X;
   sa.p = p;
   sa.q = q;
-  sa.phiT = base + offs[9];
-  sa.psiT = base + offs[10];
-  sa.phi64 = reinterpret_cast<double*>(base + offs[7]);
-  sa.psi64 = reinterpret_cast<double*>(base + offs[8]);
-  sa.st = c->st;
   sa.colpart = base + offs[2];
   sa.rowpart = base + offs[3];
   sa.tiles = reinterpret_cast<double*>(base + offs[4]);
+  sa.a = reinterpret_cast<double*>(base + offs[5]);
+  sa.b = reinterpret_cast<double*>(base + offs[6]);
+  sa.phi64 = reinterpret_cast<double*>(base + offs[7]);
+  sa.psi64 = reinterpret_cast<double*>(base + offs[8]);
+  sa.phiT = base + offs[9];
+  sa.psiT = base + offs[10];
+  sa.blockpart = reinterpret_cast<double*>(base + offs[11]);
+  sa.mu0 = mu0;
+  sa.nu0 = nu0;
+  sa.st = c->st;
+  sa.trace = c->trace;
+  sa.wall_rate = c->wall_rate;
   sa.g = g.g;
-
-  AuxArgs& aa = c->aa;
-  aa = AuxArgs{};
-  aa.p = p;
-  aa.q = q;
-  aa.colpart = sa.colpart;
-  aa.rowpart = sa.rowpart;
-  aa.tiles = sa.tiles;
-  aa.a = reinterpret_cast<double*>(base + offs[5]);
-  aa.b = reinterpret_cast<double*>(base + offs[6]);
-  aa.phi64 = reinterpret_cast<double*>(base + offs[7]);
-  aa.psi64 = reinterpret_cast<double*>(base + offs[8]);
-  aa.phiT = base + offs[9];
-  aa.psiT = base + offs[10];
-  aa.mu0 = mu0;
-  aa.nu0 = nu0;
-  aa.blockpart = reinterpret_cast<double*>(base + offs[11]);
-  aa.trace = c->trace;
-  aa.st = c->st;
-  aa.m = m;
-  aa.n = n;
-  aa.n_ct = g.g.n_ct;
-  aa.n_rb = g.g.n_rb;
-  aa.n_tiles = g.n_tiles;
-  aa.row_blocks = g.row_blocks;
-  aa.col_blocks = g.col_blocks;
-  aa.wall_rate = c->wall_rate;
 
   // Problem block of the device state.
   DevState* h = c->st_host;
@@ -417,10 +438,10 @@ int drot_bind(drot_ctx* c, int64_t m, int64_t n, int dtype, const void* C, int64
   h->m = m;
   h->n = n;
   HIP_TRY(hipMemcpyAsync(c->st, h, sizeof(DevState), hipMemcpyHostToDevice, s));
-  HIP_TRY(launch_prep(aa, s));
+  HIP_TRY(launch_prep(sa, s));
   const int mode = prm->x0_mode == DROT_X0_GIVEN ? kInitX : kInitPQ;
   HIP_TRY(launch_sweep(dtype, mode, g.vec, g.chunks, sa, s));
-  HIP_TRY(launch_aux(dtype, mode, aa, s));
+  HIP_TRY(launch_aux(dtype, mode, sa, s));
   HIP_TRY(hipMemcpyAsync(h, c->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
 
@@ -455,7 +476,7 @@ int drot_iterate(drot_ctx* c, int64_t iters, void* stream) {
       const int k = (int)std::min<int64_t>(G, iters - done);
       for (int t = 0; t < k; ++t)
         if ((rc = launch_iteration(c, s, timed ? c->ev[2 * t] : nullptr,
-                                   timed ? c->ev[2 * t + 1] : nullptr, false)))
+                                   timed ? c->ev[2 * t + 1] : nullptr)))
           return rc;
       if (timed) {
         HIP_TRY(hipStreamSynchronize(s));
@@ -481,7 +502,7 @@ int drot_iterate(drot_ctx* c, int64_t iters, void* stream) {
     if (timed && (rc = ensure_events(c, 2 * rest))) return rc;
     for (int t = 0; t < rest; ++t)
       if ((rc = launch_iteration(c, s, timed ? c->ev[2 * t] : nullptr,
-                                 timed ? c->ev[2 * t + 1] : nullptr, false)))
+                                 timed ? c->ev[2 * t + 1] : nullptr)))
         return rc;
     if (timed) {
       HIP_TRY(hipStreamSynchronize(s));
@@ -509,11 +530,11 @@ int drot_finish(drot_ctx* c, double* mu, double* nu, drot_result* out, void* str
   if (!c->bound) return fail(DROT_ESTATE, "no problem bound");
   if (!out) return fail(DROT_EINVAL, "out is NULL");
   hipStream_t s = (hipStream_t)stream;
-  AuxArgs aa = c->aa;
-  aa.mu_out = mu;
-  aa.nu_out = nu;
-  HIP_TRY(launch_sweep(c->dtype, kFinal, c->geo.vec, c->geo.chunks, c->sa, s));
-  HIP_TRY(launch_aux(c->dtype, kFinal, aa, s));
+  SweepArgs sa = c->sa;
+  sa.mu_out = mu;
+  sa.nu_out = nu;
+  HIP_TRY(launch_sweep(c->dtype, kFinal, c->geo.vec, c->geo.chunks, sa, s));
+  HIP_TRY(launch_aux(c->dtype, kFinal, sa, s));
   HIP_TRY(hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   const DevState* h = c->st_host;

@@ -10,36 +10,43 @@ namespace drot {
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kWaves = 4;          // waves per sweep workgroup
 constexpr int kBlock = kWave * kWaves;
-constexpr int kAuxBlock = 256;     // threads per aux workgroup
-constexpr int kTileSlots = 4;      // per-tile scalar partials (see TileSlot)
-constexpr int kAuxSlots = 13;      // per-aux-block scalar partials (see AuxSlot)
+constexpr int kTileSlots = 2;      // per-tile scalar partials (see TileSlot)
+constexpr int kSlots = 13;         // per-finisher scalar partials (see Slot)
 constexpr int kTraceCap = 65536;   // per-iteration records kept on the device
 constexpr int kTraceWidth = 8;
+constexpr int kAuxCols = 64;       // columns per aux workgroup
 
-// What one sweep launch does.
+// Workgroups of one aux launch: column groups of kAuxCols, then rows by kBlock.
+inline int64_t aux_workgroups(int64_t m, int64_t n) {
+  return (n + kAuxCols - 1) / kAuxCols + (m + kBlock - 1) / kBlock;
+}
+
+// What one sweep + aux pair does.
 enum SweepMode : int {
-  kIter = 0,    // Algorithm 1 step 4 + the sums of step 5, <C,X>, r_dual partial
-  kInitPQ = 1,  // write X_0 = p q^T; its row/column sums; |C|_F^2; finiteness
-  kInitX = 2,   // X_0 given: its row/column sums; |C|_F^2; finiteness
-  kFinal = 3,   // read-only FP64 evaluation of (X, phi, psi)
+  kIter = 0,    // Algorithm 1 steps 4-8 and the stopping test
+  kInitPQ = 1,  // steps 1-2 with X_0 = p q^T written; |C|_F; finiteness checks
+  kInitX = 2,   // steps 1-2 with X_0 given (read only)
+  kFinal = 3,   // read-only FP64 evaluation of (X, phi, psi); writes mu, nu
 };
 
-enum TileSlot : int { kTsCost = 0, kTsDual = 1, kTsCsq = 2, kTsBad = 3 };
+// Per-tile scalars: iteration/final: <C,X> and sum [t]_+^2; init: |C|^2 and
+// the count of non-finite entries.
+enum TileSlot : int { kTs0 = 0, kTs1 = 1 };
 
-enum AuxSlot : int {
-  kAsR = 0,     // sum r_i            (rows)
-  kAsR2,        // sum r_i^2
-  kAsPphi,      // sum p_i * phi_i    (phi without its scalar part, except kFinal)
-  kAsS,         // sum s_j            (columns)
-  kAsS2,        // sum s_j^2
-  kAsQpsi,      // sum q_j * psi_j
-  kAsT0,        // tile slot kTsCost (or kTsCsq in init), reduced over a tile range
-  kAsT1,        // tile slot kTsDual (or kTsBad in init)
-  kAsP,         // init: sum p, later unused
-  kAsQ,         // init: sum q
-  kAsP2,        // init: sum p^2 + sum q^2
-  kAsNeg,       // init: count of negative marginal entries
-  kAsNonfin,    // init: count of non-finite marginal / warm-start entries
+enum Slot : int {
+  kSR = 0,      // sum r_i  (init: sum a_i)
+  kSR2,         // sum r_i^2
+  kSPphi,       // sum p_i phi_i (phi without its scalar part, except in kFinal)
+  kSS,          // sum s_j  (init: sum b_j)
+  kSS2,         // sum s_j^2
+  kSQpsi,       // sum q_j psi_j
+  kST0,         // tile slot kTs0 summed over a slice of tiles
+  kST1,         // tile slot kTs1
+  kSP,          // init: sum p
+  kSQ,          // init: sum q
+  kSPQ2,        // init: sum p^2 + sum q^2
+  kSNeg,        // init: count of negative marginal entries
+  kSNonfin,     // init: count of non-finite marginal / warm-start entries
 };
 
 // Scalars of the iteration, resident on the device.  The host writes the
@@ -66,7 +73,7 @@ struct DevState {
   double pobj, dobj, rp, rd, gap, test;
   // --- final evaluation ---
   double f_pobj, f_dobj, f_rp, f_rd, f_gap, f_eps_p, f_eps_d, f_eps_g;
-  // --- aux completion counter (last workgroup finishes the scalars) ---
+  // --- completion counter of the finishers (the last one does the scalars) ---
   uint32_t counter, pad1;
 };
 
@@ -74,7 +81,8 @@ struct DevState {
 struct SweepGeom {
   int64_t m, n;
   int64_t ldc, ldx;
-  int n_ct;         // column tiles
+  int64_t ldcp;     // row stride of colpart (n rounded up to a multiple of 4)
+  int n_ct;         // column strips
   int n_rb;         // row blocks
   int rows;         // rows per workgroup tile
 };
@@ -82,50 +90,33 @@ struct SweepGeom {
 struct SweepArgs {
   const void* C;
   void* X;
-  const void* p;           // typed like X (init only)
-  const void* q;
-  const void* phiT;        // typed like X: phi without its scalar part
-  const void* psiT;
-  const double* phi64;     // final pass: phi without its scalar part (FP64)
-  const double* psi64;
-  DevState* st;
-  void* colpart;           // [n_rb][n]  (float in the FP32 iteration, else double)
-  void* rowpart;           // [n_ct][m]
-  double* tiles;           // [n_tiles][kTileSlots]
-  SweepGeom g;
-};
-
-struct AuxArgs {
   const void* p;           // typed like X
   const void* q;
-  const void* colpart;
-  const void* rowpart;
-  const double* tiles;
-  double* a;               // [m]
-  double* b;               // [n]
-  double* phi64;           // [m]
-  double* psi64;           // [n]
-  void* phiT;              // [m] typed like X
+  void* phiT;              // [m] typed like X: phi without its scalar part
   void* psiT;              // [n]
+  double* phi64;           // [m] the same in FP64
+  double* psi64;           // [n]
+  double* a;               // [m] accumulator a_k
+  double* b;               // [n] accumulator b_k
   const double* mu0;       // warm start (init only), may be null
   const double* nu0;
   double* mu_out;          // final only, may be null
   double* nu_out;
-  double* blockpart;       // [nblocks][kAuxSlots]
-  double* trace;           // [kTraceCap][kTraceWidth]
   DevState* st;
-  int64_t m, n;
-  int n_ct, n_rb;          // producers of rowpart / colpart
-  int n_tiles;
-  int row_blocks, col_blocks;
+  void* colpart;           // [n_rb][ldcp] (float in the FP32 iteration, else double)
+  void* rowpart;           // [n_ct][m]
+  double* tiles;           // [n_rb * n_ct][kTileSlots], tile (rb, ct) at rb * n_ct + ct
+  double* blockpart;       // [aux workgroups][kSlots]
+  double* trace;           // [kTraceCap][kTraceWidth]
   double wall_rate;        // wall_clock64 ticks per second
+  SweepGeom g;
 };
 
 // Launchers (drot_kernels.hip).  `vec` is 4 (float) / 2 (double) for 16-byte
 // loads or 1 for the scalar fallback; `chunks` the chunks per lane.
 hipError_t launch_sweep(int dtype, int mode, int vec, int chunks, const SweepArgs& a,
                         hipStream_t s);
-hipError_t launch_aux(int dtype, int mode, const AuxArgs& a, hipStream_t s);
-hipError_t launch_prep(const AuxArgs& a, hipStream_t s);
+hipError_t launch_aux(int dtype, int mode, const SweepArgs& a, hipStream_t s);
+hipError_t launch_prep(const SweepArgs& a, hipStream_t s);
 
 }  // namespace drot

@@ -1,43 +1,51 @@
 // HIP kernels of the DROT hot path for gfx950 (CDNA4, wave64).
 //
 // One iteration of Algorithm 1 (DROT) is two launches:
-//   sweep : one fused pass over the dense m x n plan.  Each entry is read
-//           once (X and C) and written once (X):
-//             t     = phi_i + psi_j - rho c_ij
-//             x_ij <- max(x_ij + t, 0)                  (Algorithm 1, step 4)
-//           and in the same pass the row sums u = X e, the column sums
-//           v = X^T f (step 5), <C, X_{k+1}> and sum [t]_+^2, which is
-//           rho^2 r_dual^2 at the incoming shifts (Section 3, stopping
-//           criteria).  Reductions are two-level and run in a fixed order:
-//           per-tile partials (rowpart, colpart, tiles) are written here and
-//           summed by the aux kernel.  No floating-point atomics anywhere.
-//   aux   : the O(m+n) part (steps 5-8): level-2 sums u, v; r = u - p,
-//           s = v - q; the shift vectors without their common scalar part,
-//           phi~ = (a - 2r)/n, psi~ = (b - 2s)/m; a -= r, b -= s; block
-//           partials.  The last workgroup to finish reduces the block
-//           partials in a fixed order and does the scalar bookkeeping:
-//           beta = f^T r/(m+n), the scalar parts (2 beta - alpha)/n and
-//           (2 beta - alpha)/m of the new shifts, alpha -= beta, and the
-//           stopping test.
-// The split phi = phi~ + (2 beta - alpha)/n is the algebra of steps 6-7
-// written so that no second pass over the vectors is needed once beta is
-// known; the sweep adds the two scalar parts to the row shift.
 //
-// The paper's kernel (Section 3, "Main kernel") is column-major, assigns one
-// thread per row and combines column sums with float atomics.  Here X is
-// row-major, a wavefront's 64 lanes run along a row with 16-byte loads, each
-// lane keeps the column partials of its columns in registers over the tile's
-// rows, row sums use DPP cross-lane reductions, and every sum is
-// deterministic.
+//  sweep_kernel  one fused pass over the dense m x n plan.  Each entry is read
+//                once (X and C) and written once (X):
+//                    t     = phi_i + psi_j - rho c_ij
+//                    x_ij <- max(x_ij + t, 0)                       (step 4)
+//                and in the same pass the kernel accumulates row sums, column
+//                sums (step 5), <C, X_{k+1}> and sum [t]_+^2 = rho^2 r_dual^2
+//                at the incoming shifts (Section 3, stopping criteria), and
+//                writes them as per-tile partials.
+//  aux_kernel    the O(m+n) part: level-2 sums of the partials in a fixed
+//                order; r = u - p, s = v - q; the vector parts of the new
+//                shifts phi~ = (a - 2r)/n, psi~ = (b - 2s)/m; a <- a - r,
+//                b <- b - s (steps 5-8).  The last workgroup to finish sums
+//                the workgroups' scalar partials in a fixed order and does the
+//                scalar steps: beta = f^T r/(m+n), the common scalar part
+//                (2 beta - alpha) of the new shifts, alpha <- alpha - beta,
+//                and the stopping test.
+//
+// The shifts are kept as phi = phi~ + (2 beta - alpha)/n and
+// psi = psi~ + (2 beta - alpha)/m (the algebra of steps 6-7): the vector parts
+// need no global quantity, and the next sweep adds the two scalar parts to its
+// row shift, so no second pass over the vectors is needed once beta is known.
+//
+// Every sum runs in a fixed order, so results are bit-reproducible; the only
+// atomics are the integer counter that elects the last aux workgroup.
+//
+// Differences from the paper's CUDA kernel (Section 3, "Main kernel"): that
+// kernel is column-major with one thread per row and sums columns with float
+// atomics.  Here X is row-major, the 64 lanes of a wavefront run along a row
+// with 16-byte loads, each lane keeps the column partials of its columns in
+// registers over the tile's rows, row sums use DPP cross-lane reductions, and
+// column partials go through a deterministic two-level tree.  The kernel
+// boundary between sweep and aux is the device-wide release/acquire point: a
+// device-scope fence inside the sweep would write back the L2 (full of the
+// freshly written plan) once per workgroup.
+#include <type_traits>
+
 #include "drot_internal.h"
 
 namespace drot {
 namespace {
 
 // ---------------------------------------------------------------------------
-// Wave-level sum with DPP (all 64 lanes active).  The combination order is
-// fixed, so the result is bit-reproducible.  Result is valid in lane 63 and
-// broadcast through readlane.
+// Wave-level sum with DPP (all 64 lanes active).  Fixed combination order;
+// the result is read from lane 63.
 // ---------------------------------------------------------------------------
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ int dpp_i(int v) {
@@ -80,7 +88,7 @@ __device__ __forceinline__ V wave_sum(V v) {
 }
 
 // ---------------------------------------------------------------------------
-// Types.
+// Types and memory helpers.
 // ---------------------------------------------------------------------------
 template <typename T, int MODE>
 struct PartialOf {
@@ -129,10 +137,287 @@ __device__ __forceinline__ void store_chunk(T* ptr, const T (&in)[VEC]) {
 
 __device__ __forceinline__ bool finite_d(double v) { return __builtin_isfinite(v); }
 
+__device__ __forceinline__ void store_agent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_agent(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Block-wide fixed-order sum of kSlots values; result valid in thread 0.
+__device__ __forceinline__ void block_sum_slots(double (&acc)[kSlots],
+                                                double (&red)[kSlots][kWaves]) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  __syncthreads();  // `red` may still be read from a previous use
+#pragma unroll
+  for (int s = 0; s < kSlots; ++s) {
+    const double v = wave_sum(acc[s]);
+    if (lane == 0) red[s][wave] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+      double v = red[s][0];
+#pragma unroll
+      for (int w = 1; w < kWaves; ++w) v += red[s][w];
+      acc[s] = v;
+    }
+  }
+}
+
+// Run by the last aux workgroup: fixed-order sum of all workgroups' scalar
+// partials, then the scalar steps of the iteration (or of the initialisation
+// or the final evaluation).
+template <int MODE>
+__device__ void finish_global(const SweepArgs& a, int nb, double (&red)[kSlots][kWaves]) {
+  double acc[kSlots];
+#pragma unroll
+  for (int s = 0; s < kSlots; ++s) acc[s] = 0.0;
+  for (int k = threadIdx.x; k < nb; k += kBlock)
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) acc[s] += load_agent(a.blockpart + (int64_t)k * kSlots + s);
+  block_sum_slots(acc, red);
+  if (threadIdx.x != 0) return;
+
+  DevState* st = a.st;
+  const int64_t m = a.g.m, n = a.g.n;
+  const double mn = (double)(m + n);
+  const double rho = st->rho;
+  const uint64_t now = wall_clock64();
+  if (MODE == kIter) {
+    const double beta = acc[kSR] / mn;
+    const double alpha = st->alpha;
+    const double cc = 2.0 * beta - alpha;
+    const double cphi = cc / (double)n, cpsi = cc / (double)m;
+    const double pobj = acc[kST0];
+    const double dobj = (acc[kSPphi] + cphi * st->sum_p + acc[kSQpsi] + cpsi * st->sum_q) / rho;
+    const double gap = fabs(pobj - dobj);
+    const double rp = sqrt(acc[kSR2] + acc[kSS2]);
+    const double rd = sqrt(acc[kST1]) / rho;
+    const double ep = rp / fmax(st->norm_pq, 1e-300);
+    const double ed = rd / fmax(st->norm_c, 1e-300);
+    const double eg = gap / fmax(fmax(fabs(pobj), fabs(dobj)), 1e-300);
+    const double test = st->tol_mode ? fmax(rp, fmax(rd, gap)) : fmax(ep, fmax(ed, eg));
+    const int64_t k = st->iter + 1;
+    st->alpha = alpha - beta;
+    st->cphi = cphi;
+    st->cpsi = cpsi;
+    st->iter = k;
+    st->t_last = now;
+    st->pobj = pobj;
+    st->dobj = dobj;
+    st->rp = rp;
+    st->rd = rd;
+    st->gap = gap;
+    st->test = test;
+    double* tr = a.trace + ((k - 1) % kTraceCap) * kTraceWidth;
+    tr[0] = pobj;
+    tr[1] = dobj;
+    tr[2] = rp;
+    tr[3] = rd;
+    tr[4] = gap;
+    tr[5] = test;
+    tr[6] = (double)(now - st->t_start) / a.wall_rate;
+    tr[7] = (double)k;
+    int done = 0, status = 0;
+    if (!finite_d(test) || !finite_d(st->alpha) || !finite_d(cc)) {
+      done = 1;
+      status = -3;
+    } else if (test <= st->tol) {
+      done = 1;
+      status = 0;
+    } else if (k >= st->max_iter) {
+      done = 1;
+      status = 1;
+    }
+    if (done) {
+      st->done = 1;
+      st->status = status;
+      st->stop_iter = k;
+      st->t_stop = now;
+    }
+  } else if (MODE == kFinal) {
+    const double pobj = acc[kST0];
+    const double dobj = (acc[kSPphi] + acc[kSQpsi]) / rho;
+    st->f_pobj = pobj;
+    st->f_dobj = dobj;
+    st->f_rp = sqrt(acc[kSR2] + acc[kSS2]);
+    st->f_rd = sqrt(acc[kST1]) / rho;
+    st->f_gap = fabs(pobj - dobj);
+    st->f_eps_p = st->f_rp / fmax(st->norm_pq, 1e-300);
+    st->f_eps_d = st->f_rd / fmax(st->norm_c, 1e-300);
+    st->f_eps_g = st->f_gap / fmax(fmax(fabs(pobj), fabs(dobj)), 1e-300);
+  } else {
+    st->alpha = acc[kSR] / mn;
+    st->sum_p = acc[kSP];
+    st->sum_q = acc[kSQ];
+    st->norm_pq = sqrt(acc[kSPQ2]);
+    st->norm_c = sqrt(acc[kST0]);
+    st->init_bad = acc[kST1] + acc[kSNonfin];
+    st->init_neg = acc[kSNeg];
+    st->cphi = 0.0;
+    st->cpsi = 0.0;
+    st->iter = 0;
+    st->done = 0;
+    st->status = 0;
+    st->stop_iter = 0;
+    st->t_last = now;
+  }
+}
+
 // ---------------------------------------------------------------------------
-// The fused sweep.  Tile = `rows` rows x W columns, W = 64 * VEC * CH.  The
-// four waves of a workgroup split the tile's rows into contiguous slices;
-// each lane owns CH chunks of VEC consecutive columns.
+// The O(m+n) kernel.  Workgroups [0, col_wgs) own kAuxCols columns each: the
+// column partials are read as 16-byte chunks with the row blocks split over
+// G thread groups, then combined in LDS in a fixed order.  The remaining
+// workgroups own 256 rows each.  Every workgroup also sums a fixed slice of
+// the tile scalars.  The last workgroup to finish does the scalar steps.
+// ---------------------------------------------------------------------------
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void aux_kernel(SweepArgs a) {
+  using P = typename PartialOf<T, MODE>::type;
+  constexpr int CW = 16 / sizeof(P);      // columns per 16-byte chunk
+  constexpr int NCH = kAuxCols / CW;      // chunks per workgroup
+  constexpr int G = kBlock / NCH;         // row-block groups
+  using V = typename VecOf<P, CW>::type;
+
+  DevState* st = a.st;
+  if (MODE == kIter && st->done) return;
+
+  __shared__ double red2[G * kAuxCols];
+  __shared__ double red[kSlots][kWaves];
+  __shared__ int last;
+
+  double acc[kSlots];
+#pragma unroll
+  for (int s = 0; s < kSlots; ++s) acc[s] = 0.0;
+  const int64_t m = a.g.m, n = a.g.n;
+  const int col_wgs = (int)((n + kAuxCols - 1) / kAuxCols);
+  const int b = blockIdx.x;
+  const int nb = gridDim.x;
+  const double rho = st->rho;
+
+  if (b < col_wgs) {
+    const int64_t j0 = (int64_t)b * kAuxCols;
+    {
+      const int ch = threadIdx.x % NCH, grp = threadIdx.x / NCH;
+      const int n_rb = a.g.n_rb;
+      const int r0 = (int)((int64_t)n_rb * grp / G), r1 = (int)((int64_t)n_rb * (grp + 1) / G);
+      const P* cp = static_cast<const P*>(a.colpart) + j0 + ch * CW;
+      double s[CW];
+#pragma unroll
+      for (int e = 0; e < CW; ++e) s[e] = 0.0;
+      for (int r = r0; r < r1; ++r) {
+        const V v = *reinterpret_cast<const V*>(cp + (int64_t)r * a.g.ldcp);
+#pragma unroll
+        for (int e = 0; e < CW; ++e) s[e] += (double)v[e];
+      }
+#pragma unroll
+      for (int e = 0; e < CW; ++e) red2[grp * kAuxCols + ch * CW + e] = s[e];
+    }
+    __syncthreads();
+    const int64_t j = j0 + threadIdx.x;
+    if (threadIdx.x < kAuxCols && j < n) {
+      double v = red2[threadIdx.x];
+#pragma unroll
+      for (int g = 1; g < G; ++g) v += red2[g * kAuxCols + threadIdx.x];
+      const double qj = (double)static_cast<const T*>(a.q)[j];
+      const double s = v - qj;
+      if (MODE == kIter) {
+        const double bj = a.b[j];
+        const double ps = (bj - 2.0 * s) / (double)m;
+        a.b[j] = bj - s;
+        a.psi64[j] = ps;
+        static_cast<T*>(a.psiT)[j] = (T)ps;
+        acc[kSS] = s;
+        acc[kSS2] = s * s;
+        acc[kSQpsi] = qj * ps;
+      } else if (MODE == kFinal) {
+        const double ps = a.psi64[j] + st->cpsi;
+        acc[kSS2] = s * s;
+        acc[kSQpsi] = qj * ps;
+        if (a.nu_out) a.nu_out[j] = ps / rho;
+      } else {
+        const double ps0 = a.nu0 ? rho * a.nu0[j] : 0.0;
+        const double bj = v - qj + (double)m * ps0 + st->sum_phi0;
+        a.b[j] = bj;
+        a.psi64[j] = ps0;
+        static_cast<T*>(a.psiT)[j] = (T)ps0;
+        acc[kSS] = bj;
+        acc[kSQ] = qj;
+        acc[kSPQ2] = qj * qj;
+        acc[kSNeg] = qj < 0.0 ? 1.0 : 0.0;
+        acc[kSNonfin] = (!finite_d(qj) || !finite_d(ps0)) ? 1.0 : 0.0;
+      }
+    }
+  } else {
+    const int64_t i = (int64_t)(b - col_wgs) * kBlock + threadIdx.x;
+    if (i < m) {
+      const P* rp = static_cast<const P*>(a.rowpart);
+      double u = 0.0;
+      for (int c = 0; c < a.g.n_ct; ++c) u += (double)rp[(int64_t)c * m + i];
+      const double pi = (double)static_cast<const T*>(a.p)[i];
+      const double r = u - pi;
+      if (MODE == kIter) {
+        const double ai = a.a[i];
+        const double ph = (ai - 2.0 * r) / (double)n;
+        a.a[i] = ai - r;
+        a.phi64[i] = ph;
+        static_cast<T*>(a.phiT)[i] = (T)ph;
+        acc[kSR] = r;
+        acc[kSR2] = r * r;
+        acc[kSPphi] = pi * ph;
+      } else if (MODE == kFinal) {
+        const double ph = a.phi64[i] + st->cphi;
+        acc[kSR2] = r * r;
+        acc[kSPphi] = pi * ph;
+        if (a.mu_out) a.mu_out[i] = ph / rho;
+      } else {
+        const double ph0 = a.mu0 ? rho * a.mu0[i] : 0.0;
+        const double ai = u - pi + (double)n * ph0 + st->sum_psi0;
+        a.a[i] = ai;
+        a.phi64[i] = ph0;
+        static_cast<T*>(a.phiT)[i] = (T)ph0;
+        acc[kSR] = ai;
+        acc[kSP] = pi;
+        acc[kSPQ2] = pi * pi;
+        acc[kSNeg] = pi < 0.0 ? 1.0 : 0.0;
+        acc[kSNonfin] = (!finite_d(pi) || !finite_d(ph0)) ? 1.0 : 0.0;
+      }
+    }
+  }
+
+  // A fixed slice of the sweep's tile scalars.
+  {
+    const int64_t nt = (int64_t)a.g.n_ct * a.g.n_rb;
+    const int64_t t0 = nt * b / nb, t1 = nt * (b + 1) / nb;
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += kBlock) {
+      acc[kST0] += a.tiles[t * kTileSlots + kTs0];
+      acc[kST1] += a.tiles[t * kTileSlots + kTs1];
+    }
+  }
+
+  block_sum_slots(acc, red);
+  if (threadIdx.x == 0) {
+    for (int s = 0; s < kSlots; ++s) store_agent(a.blockpart + (int64_t)b * kSlots + s, acc[s]);
+    __threadfence();
+    const unsigned prev = atomicAdd(&st->counter, 1u);
+    last = prev == (unsigned)(nb - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  finish_global<MODE>(a, nb, red);
+  if (threadIdx.x == 0)
+    __hip_atomic_store(&st->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
+// The sweep.  Tile = `rows` rows x W columns, W = 64 * VEC * CH.  The four
+// waves of a workgroup split the tile's rows into contiguous slices; each
+// lane owns CH chunks of VEC consecutive columns.  Consecutive workgroups
+// take consecutive column strips of the same row block.
 // ---------------------------------------------------------------------------
 template <typename T, int MODE, int VEC, int CH>
 __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a) {
@@ -142,7 +427,7 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a) {
   constexpr int W = kWave * CPL;
   constexpr int U = 4;
 
-  const DevState* st = a.st;
+  DevState* st = a.st;
   if (MODE == kIter && st->done) return;
 
   const int lane = threadIdx.x & (kWave - 1);
@@ -265,298 +550,54 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a) {
     }
   }
 
-  // Column partials: combine the four waves' registers in LDS, fixed order.
-  __shared__ P sm[kWaves][W];
-  __shared__ double ssc[kWaves][2];
+  // ---- tile partials: combine the four waves in LDS, fixed order -----------
+  __shared__ P sm[kWaves * W];
+  __shared__ double ssc[2][kWaves];
 #pragma unroll
   for (int c = 0; c < CH; ++c)
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) sm[wave][c * kWave * VEC + lane * VEC + e] = colacc[c][e];
+    for (int e = 0; e < VEC; ++e) sm[wave * W + c * kWave * VEC + lane * VEC + e] = colacc[c][e];
   const P w0 = wave_sum(s0);
   const P w1 = wave_sum(s1);
   if (lane == 0) {
-    ssc[wave][0] = (double)w0;
-    ssc[wave][1] = (double)w1;
+    ssc[0][wave] = (double)w0;
+    ssc[1][wave] = (double)w1;
   }
   __syncthreads();
   P* __restrict__ colpart = static_cast<P*>(a.colpart);
   for (int k = threadIdx.x; k < W; k += kBlock) {
     const int64_t j = col0 + k;
     if (j < n) {
-      P v = sm[0][k];
+      P v = sm[k];
 #pragma unroll
-      for (int w = 1; w < kWaves; ++w) v += sm[w][k];
-      colpart[(int64_t)rb * n + j] = v;
+      for (int w = 1; w < kWaves; ++w) v += sm[w * W + k];
+      colpart[(int64_t)rb * a.g.ldcp + j] = v;
     }
   }
   if (threadIdx.x == 0) {
-    double v0 = ssc[0][0], v1 = ssc[0][1];
+    double v0 = ssc[0][0], v1 = ssc[1][0];
 #pragma unroll
     for (int w = 1; w < kWaves; ++w) {
-      v0 += ssc[w][0];
-      v1 += ssc[w][1];
+      v0 += ssc[0][w];
+      v1 += ssc[1][w];
     }
-    double* t = a.tiles + (int64_t)blockIdx.x * kTileSlots;
-    if (MODE == kIter || MODE == kFinal) {
-      t[kTsCost] = v0;
-      t[kTsDual] = v1;
-    } else {
-      t[kTsCsq] = v0;
-      t[kTsBad] = v1;
-    }
+    double* t = a.tiles + ((int64_t)rb * a.g.n_ct + ct) * kTileSlots;
+    t[kTs0] = v0;
+    t[kTs1] = v1;
   }
 }
 
-// ---------------------------------------------------------------------------
-// Block-wide fixed-order sum of kAuxSlots values, result valid in thread 0.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void block_sum_slots(double (&acc)[kAuxSlots],
-                                                double (&red)[kAuxSlots][kAuxBlock / kWave]) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
+// Warm-start sums sum(phi_0) = rho sum(mu0), sum(psi_0) = rho sum(nu0), the
+// start timestamp, and zeroed completion counters.  One workgroup.
+__global__ __launch_bounds__(kBlock) void prep_kernel(SweepArgs a) {
+  __shared__ double red[kSlots][kWaves];
+  double acc[kSlots];
 #pragma unroll
-  for (int s = 0; s < kAuxSlots; ++s) {
-    const double v = wave_sum(acc[s]);
-    if (lane == 0) red[s][wave] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int s = 0; s < kAuxSlots; ++s) {
-      double v = red[s][0];
-      for (int w = 1; w < kAuxBlock / kWave; ++w) v += red[s][w];
-      acc[s] = v;
-    }
-  }
-}
-
-__device__ __forceinline__ void store_agent(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double load_agent(const double* p) {
-  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// ---------------------------------------------------------------------------
-// The O(m+n) kernel.  Workgroups [0, row_blocks) own rows, the rest columns.
-// ---------------------------------------------------------------------------
-template <typename T, int MODE>
-__global__ __launch_bounds__(kAuxBlock) void aux_kernel(AuxArgs a) {
-  using P = typename PartialOf<T, MODE>::type;
-  DevState* st = a.st;
-  if (MODE == kIter && st->done) return;
-
-  __shared__ double red[kAuxSlots][kAuxBlock / kWave];
-  __shared__ int am_last;
-
-  double acc[kAuxSlots];
-#pragma unroll
-  for (int s = 0; s < kAuxSlots; ++s) acc[s] = 0.0;
-
-  const int b = blockIdx.x;
-  const int nb = gridDim.x;
-  const double rho = st->rho;
-  const int64_t m = a.m, n = a.n;
-
-  if (b < a.row_blocks) {
-    const int64_t i = (int64_t)b * kAuxBlock + threadIdx.x;
-    if (i < m) {
-      const P* rp = static_cast<const P*>(a.rowpart);
-      double u = 0.0;
-      for (int c = 0; c < a.n_ct; ++c) u += (double)rp[(int64_t)c * m + i];
-      const double pi = (double)static_cast<const T*>(a.p)[i];
-      const double r = u - pi;
-      if (MODE == kIter) {
-        const double ai = a.a[i];
-        const double ph = (ai - 2.0 * r) / (double)n;
-        a.a[i] = ai - r;
-        a.phi64[i] = ph;
-        static_cast<T*>(a.phiT)[i] = (T)ph;
-        acc[kAsR] = r;
-        acc[kAsR2] = r * r;
-        acc[kAsPphi] = pi * ph;
-      } else if (MODE == kFinal) {
-        const double ph = a.phi64[i] + st->cphi;
-        acc[kAsR2] = r * r;
-        acc[kAsPphi] = pi * ph;
-        if (a.mu_out) a.mu_out[i] = ph / rho;
-      } else {
-        const double ph0 = a.mu0 ? rho * a.mu0[i] : 0.0;
-        const double ai = u - pi + (double)n * ph0 + st->sum_psi0;
-        a.a[i] = ai;
-        a.phi64[i] = ph0;
-        static_cast<T*>(a.phiT)[i] = (T)ph0;
-        acc[kAsR] = ai;
-        acc[kAsP] = pi;
-        acc[kAsP2] = pi * pi;
-        acc[kAsNeg] = pi < 0.0 ? 1.0 : 0.0;
-        acc[kAsNonfin] = (!finite_d(pi) || !finite_d(ph0)) ? 1.0 : 0.0;
-      }
-    }
-  } else {
-    const int64_t j = (int64_t)(b - a.row_blocks) * kAuxBlock + threadIdx.x;
-    if (j < n) {
-      const P* cp = static_cast<const P*>(a.colpart);
-      double v = 0.0;
-      for (int r = 0; r < a.n_rb; ++r) v += (double)cp[(int64_t)r * n + j];
-      const double qj = (double)static_cast<const T*>(a.q)[j];
-      const double s = v - qj;
-      if (MODE == kIter) {
-        const double bj = a.b[j];
-        const double ps = (bj - 2.0 * s) / (double)m;
-        a.b[j] = bj - s;
-        a.psi64[j] = ps;
-        static_cast<T*>(a.psiT)[j] = (T)ps;
-        acc[kAsS] = s;
-        acc[kAsS2] = s * s;
-        acc[kAsQpsi] = qj * ps;
-      } else if (MODE == kFinal) {
-        const double ps = a.psi64[j] + st->cpsi;
-        acc[kAsS2] = s * s;
-        acc[kAsQpsi] = qj * ps;
-        if (a.nu_out) a.nu_out[j] = ps / rho;
-      } else {
-        const double ps0 = a.nu0 ? rho * a.nu0[j] : 0.0;
-        const double bj = v - qj + (double)m * ps0 + st->sum_phi0;
-        a.b[j] = bj;
-        a.psi64[j] = ps0;
-        static_cast<T*>(a.psiT)[j] = (T)ps0;
-        acc[kAsS] = bj;
-        acc[kAsQ] = qj;
-        acc[kAsP2] = qj * qj;
-        acc[kAsNeg] = qj < 0.0 ? 1.0 : 0.0;
-        acc[kAsNonfin] = (!finite_d(qj) || !finite_d(ps0)) ? 1.0 : 0.0;
-      }
-    }
-  }
-
-  // A fixed slice of the sweep's tile partials.
-  {
-    const int64_t t0 = (int64_t)a.n_tiles * b / nb;
-    const int64_t t1 = (int64_t)a.n_tiles * (b + 1) / nb;
-    const int sl0 = (MODE == kIter || MODE == kFinal) ? kTsCost : kTsCsq;
-    const int sl1 = (MODE == kIter || MODE == kFinal) ? kTsDual : kTsBad;
-    for (int64_t t = t0 + threadIdx.x; t < t1; t += kAuxBlock) {
-      acc[kAsT0] += a.tiles[t * kTileSlots + sl0];
-      acc[kAsT1] += a.tiles[t * kTileSlots + sl1];
-    }
-  }
-
-  block_sum_slots(acc, red);
-  if (threadIdx.x == 0) {
-    for (int s = 0; s < kAuxSlots; ++s) store_agent(a.blockpart + (int64_t)b * kAuxSlots + s, acc[s]);
-    __threadfence();
-    const unsigned prev = atomicAdd(&st->counter, 1u);
-    am_last = (prev == (unsigned)(nb - 1));
-  }
-  __syncthreads();
-  if (!am_last) return;
-  __threadfence();
-
-  // Last workgroup: fixed-order reduction of the block partials.
-#pragma unroll
-  for (int s = 0; s < kAuxSlots; ++s) acc[s] = 0.0;
-  for (int k = threadIdx.x; k < nb; k += kAuxBlock)
-#pragma unroll
-    for (int s = 0; s < kAuxSlots; ++s) acc[s] += load_agent(a.blockpart + (int64_t)k * kAuxSlots + s);
-  __syncthreads();
-  block_sum_slots(acc, red);
-  if (threadIdx.x != 0) return;
-
-  const double mn = (double)(m + n);
-  const uint64_t now = wall_clock64();
-  if (MODE == kIter) {
-    const double beta = acc[kAsR] / mn;
-    const double alpha = st->alpha;
-    const double cc = 2.0 * beta - alpha;
-    const double cphi = cc / (double)n, cpsi = cc / (double)m;
-    const double pobj = acc[kAsT0];
-    const double dobj = (acc[kAsPphi] + cphi * st->sum_p + acc[kAsQpsi] + cpsi * st->sum_q) / rho;
-    const double gap = fabs(pobj - dobj);
-    const double rp = sqrt(acc[kAsR2] + acc[kAsS2]);
-    const double rd = sqrt(acc[kAsT1]) / rho;
-    const double ep = rp / fmax(st->norm_pq, 1e-300);
-    const double ed = rd / fmax(st->norm_c, 1e-300);
-    const double eg = gap / fmax(fmax(fabs(pobj), fabs(dobj)), 1e-300);
-    const double test = st->tol_mode ? fmax(rp, fmax(rd, gap)) : fmax(ep, fmax(ed, eg));
-    const int64_t k = st->iter + 1;
-    st->alpha = alpha - beta;
-    st->cphi = cphi;
-    st->cpsi = cpsi;
-    st->iter = k;
-    st->t_last = now;
-    st->pobj = pobj;
-    st->dobj = dobj;
-    st->rp = rp;
-    st->rd = rd;
-    st->gap = gap;
-    st->test = test;
-    double* tr = a.trace + ((k - 1) % kTraceCap) * kTraceWidth;
-    tr[0] = pobj;
-    tr[1] = dobj;
-    tr[2] = rp;
-    tr[3] = rd;
-    tr[4] = gap;
-    tr[5] = test;
-    tr[6] = (double)(now - st->t_start) / a.wall_rate;
-    tr[7] = (double)k;
-    int done = 0, status = 0;
-    if (!finite_d(test) || !finite_d(st->alpha) || !finite_d(cc)) {
-      done = 1;
-      status = -3;
-    } else if (test <= st->tol) {
-      done = 1;
-      status = 0;
-    } else if (k >= st->max_iter) {
-      done = 1;
-      status = 1;
-    }
-    if (done) {
-      st->done = 1;
-      st->status = status;
-      st->stop_iter = k;
-      st->t_stop = now;
-    }
-  } else if (MODE == kFinal) {
-    const double pobj = acc[kAsT0];
-    const double dobj = (acc[kAsPphi] + acc[kAsQpsi]) / rho;
-    st->f_pobj = pobj;
-    st->f_dobj = dobj;
-    st->f_rp = sqrt(acc[kAsR2] + acc[kAsS2]);
-    st->f_rd = sqrt(acc[kAsT1]) / rho;
-    st->f_gap = fabs(pobj - dobj);
-    st->f_eps_p = st->f_rp / fmax(st->norm_pq, 1e-300);
-    st->f_eps_d = st->f_rd / fmax(st->norm_c, 1e-300);
-    st->f_eps_g = st->f_gap / fmax(fmax(fabs(pobj), fabs(dobj)), 1e-300);
-  } else {
-    st->alpha = acc[kAsR] / mn;
-    st->sum_p = acc[kAsP];
-    st->sum_q = acc[kAsQ];
-    st->norm_pq = sqrt(acc[kAsP2]);
-    st->norm_c = sqrt(acc[kAsT0]);
-    st->init_bad = acc[kAsT1] + acc[kAsNonfin];
-    st->init_neg = acc[kAsNeg];
-    st->cphi = 0.0;
-    st->cpsi = 0.0;
-    st->iter = 0;
-    st->done = 0;
-    st->status = 0;
-    st->stop_iter = 0;
-  }
-  __hip_atomic_store(&st->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Warm-start sums sum(phi_0) = rho sum(mu0), sum(psi_0) = rho sum(nu0), and the
-// start timestamp.  One workgroup.
-__global__ __launch_bounds__(kAuxBlock) void prep_kernel(AuxArgs a) {
-  __shared__ double red[kAuxSlots][kAuxBlock / kWave];
-  double acc[kAuxSlots];
-#pragma unroll
-  for (int s = 0; s < kAuxSlots; ++s) acc[s] = 0.0;
+  for (int s = 0; s < kSlots; ++s) acc[s] = 0.0;
   if (a.mu0)
-    for (int64_t i = threadIdx.x; i < a.m; i += kAuxBlock) acc[0] += a.mu0[i];
+    for (int64_t i = threadIdx.x; i < a.g.m; i += kBlock) acc[0] += a.mu0[i];
   if (a.nu0)
-    for (int64_t j = threadIdx.x; j < a.n; j += kAuxBlock) acc[1] += a.nu0[j];
+    for (int64_t j = threadIdx.x; j < a.g.n; j += kBlock) acc[1] += a.nu0[j];
   block_sum_slots(acc, red);
   if (threadIdx.x == 0) {
     DevState* st = a.st;
@@ -598,13 +639,13 @@ hipError_t sweep_type(int mode, int vec, int chunks, const SweepArgs& a, hipStre
 }
 
 template <typename T>
-hipError_t aux_type(int mode, const AuxArgs& a, hipStream_t s) {
-  const dim3 grid((unsigned)(a.row_blocks + a.col_blocks));
+hipError_t aux_type(int mode, const SweepArgs& a, hipStream_t s) {
+  const dim3 grid((unsigned)aux_workgroups(a.g.m, a.g.n));
   switch (mode) {
-    case kIter: hipLaunchKernelGGL((aux_kernel<T, kIter>), grid, dim3(kAuxBlock), 0, s, a); break;
+    case kIter: hipLaunchKernelGGL((aux_kernel<T, kIter>), grid, dim3(kBlock), 0, s, a); break;
     case kInitPQ:
-    case kInitX: hipLaunchKernelGGL((aux_kernel<T, kInitPQ>), grid, dim3(kAuxBlock), 0, s, a); break;
-    case kFinal: hipLaunchKernelGGL((aux_kernel<T, kFinal>), grid, dim3(kAuxBlock), 0, s, a); break;
+    case kInitX: hipLaunchKernelGGL((aux_kernel<T, kInitPQ>), grid, dim3(kBlock), 0, s, a); break;
+    case kFinal: hipLaunchKernelGGL((aux_kernel<T, kFinal>), grid, dim3(kBlock), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -612,18 +653,18 @@ hipError_t aux_type(int mode, const AuxArgs& a, hipStream_t s) {
 
 }  // namespace
 
+hipError_t launch_aux(int dtype, int mode, const SweepArgs& a, hipStream_t s) {
+  return dtype == 0 ? aux_type<float>(mode, a, s) : aux_type<double>(mode, a, s);
+}
+
 hipError_t launch_sweep(int dtype, int mode, int vec, int chunks, const SweepArgs& a,
                         hipStream_t s) {
   return dtype == 0 ? sweep_type<float>(mode, vec, chunks, a, s)
                     : sweep_type<double>(mode, vec, chunks, a, s);
 }
 
-hipError_t launch_aux(int dtype, int mode, const AuxArgs& a, hipStream_t s) {
-  return dtype == 0 ? aux_type<float>(mode, a, s) : aux_type<double>(mode, a, s);
-}
-
-hipError_t launch_prep(const AuxArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(prep_kernel, dim3(1), dim3(kAuxBlock), 0, s, a);
+hipError_t launch_prep(const SweepArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(prep_kernel, dim3(1), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

@@ -245,3 +245,17 @@ def test_error_paths(ctx):
     X, res, mu, nu = drot.solve(C, p, q, inst.rho, tol=1e-12, max_iter=5, ctx=ctx)
     assert res["status"] == drot.MAXITER and res["iters"] == 5
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("flags", ["graph", "eager"])
+def test_timed_sweeps_change_nothing(ctx, flags):
+    """DROT_FLAG_TIME_SWEEP only adds hipEvents around the sweeps."""
+    from paper_2110_11738_amd import drot
+    inst = round_to(config_mixture_2d(4, 256, 512), np.float32)
+    base = _run(ctx, inst, "float32", 80, check_every=16)
+    fl = drot.FLAG_TIME_SWEEP | (drot.FLAG_NO_GRAPH if flags == "eager" else 0)
+    timed = _run(ctx, inst, "float32", 80, check_every=16, flags=fl)
+    np.testing.assert_array_equal(base[0], timed[0])
+    np.testing.assert_array_equal(base[2], timed[2])
+    assert timed[1]["sweep_timed"] == 80
+    assert timed[1]["sweep_ms_total"] > 0
