@@ -63,7 +63,9 @@ def timed_iterations(ctx, C, p, q, rho, steps, warmup, args, timed_events=True):
     X = torch.empty((m, n), dtype=C.dtype, device=C.device)
     flags = drot.FLAG_TIME_SWEEP if timed_events else 0
     prm = drot.make_params(rho, 0.0, warmup + steps + 1, check_every=args.check_every,
-                           flags=flags, tile_rows=args.tile_rows, tile_chunks=args.tile_chunks)
+                           flags=flags, tile_rows=args.tile_rows, tile_chunks=args.tile_chunks,
+                           tile_unroll=args.tile_unroll, cache_mode=args.cache_mode,
+                           tile_groups=args.tile_groups)
     ctx.bind(C, p, q, X, prm)
     if warmup:
         ctx.iterate(warmup)
@@ -128,6 +130,9 @@ def main():
     ap.add_argument("--no-tol", action="store_true")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--tile-chunks", type=int, default=0)
+    ap.add_argument("--tile-unroll", type=int, default=0)
+    ap.add_argument("--cache-mode", type=int, default=0, help="0 auto, 1 cached, 2 streaming")
+    ap.add_argument("--tile-groups", type=int, default=0)
     ap.add_argument("--check-every", type=int, default=64)
     args = ap.parse_args()
 
@@ -173,6 +178,8 @@ def main():
                                f"sigma 0.1, sq-Euclidean C / max, Dirichlet(1) marginals, "
                                f"rho0 = 1/ln m)", "m": m, "n": n, "rho": inst.rho,
                    "tile_rows": args.tile_rows, "tile_chunks": args.tile_chunks,
+                   "tile_unroll": args.tile_unroll, "cache_mode": args.cache_mode,
+                   "tile_groups": args.tile_groups,
                    "check_every": args.check_every, "parallelism": "single GPU"},
         "value_without_sweep_events": args.steps / secs_ne,
         "roofline": roof,
@@ -182,7 +189,9 @@ def main():
     if not args.no_tol:
         X = torch.empty((m, n), dtype=torch.float32, device="cuda")
         prm = drot.make_params(inst.rho, 1e-4, 2_000_000, check_every=args.check_every,
-                               tile_rows=args.tile_rows, tile_chunks=args.tile_chunks)
+                               tile_rows=args.tile_rows, tile_chunks=args.tile_chunks,
+                               tile_unroll=args.tile_unroll, cache_mode=args.cache_mode,
+                           tile_groups=args.tile_groups)
         X, r = ctx.solve(C, p, q, prm, X=X)
         torch.cuda.synchronize()
         out["time_to_tol"] = {"tol": 1e-4, "status": r["status"], "iters": r["iters"],

@@ -76,9 +76,23 @@ typedef enum { DROT_TOL_RELATIVE = 0, DROT_TOL_ABSOLUTE = 1 } drot_tol_mode;
  * DROT_X0_GIVEN: X holds X_0 on entry (any nonnegative matrix). */
 typedef enum { DROT_X0_PQ = 0, DROT_X0_GIVEN = 1 } drot_x0_mode;
 
+/* How the sweep's loads and stores of X and C use the caches.  Streaming
+ * (nontemporal) accesses pay off once X and C no longer fit in the 256 MB
+ * last-level cache; below that, cached accesses let iterations hit in it.
+ * DROT_CACHE_AUTO streams when X and C together exceed 192 MiB. */
+typedef enum { DROT_CACHE_AUTO = 0, DROT_CACHE_CACHED = 1, DROT_CACHE_STREAM = 2 } drot_cache_mode;
+
 /* drot_params.flags */
 #define DROT_FLAG_NO_GRAPH 0x1    /* launch eagerly instead of replaying hipGraphs */
 #define DROT_FLAG_TIME_SWEEP 0x2  /* bracket sweep launches with hipEvents (see drot_result) */
+/* The skip-C schedule of the paper's Claim 1 (Section 3, "Main kernel"):
+ * iterations alternate between one that reads X and C and stores
+ * W = X_{k+1} - rho C, and one that reads only W and stores
+ * X_{k+2} = [W + phi e^T + f psi^T]_+, so that an iteration moves 10 instead of
+ * 12 bytes per float32 entry on average.  The stopping test runs after the
+ * C-reading iterations only (the other one has no <C,X> and no r_dual);
+ * drot_finish restores X when the run ends on a C-reading iteration. */
+#define DROT_FLAG_SKIP_C 0x4
 
 typedef struct {
   double rho;          /* penalty parameter rho > 0 (the paper uses rho0/(m+n)) */
@@ -88,8 +102,15 @@ typedef struct {
   int32_t x0_mode;     /* drot_x0_mode */
   int32_t check_every; /* iterations between host polls of the stop flag; 0 = 32 */
   int32_t flags;       /* DROT_FLAG_* */
-  int32_t tile_rows;   /* rows per workgroup tile of the sweep; 0 = automatic */
-  int32_t tile_chunks; /* 16-byte column chunks per lane (1 or 2); 0 = automatic */
+  /* Sweep schedule (all 0 = automatic).  A workgroup owns a strip of
+   * 64 * tile_chunks * (16 / element size) columns and the row blocks
+   * g, g + tile_groups, g + 2 tile_groups, ... of tile_rows rows each. */
+  int32_t tile_rows;   /* rows per row block (1..4096) */
+  int32_t tile_chunks; /* 16-byte column chunks per lane (1 or 2) */
+  int32_t tile_unroll; /* rows whose loads a wave keeps in flight (4 or 8) */
+  int32_t cache_mode;  /* drot_cache_mode for the plan and cost streams */
+  int32_t tile_groups; /* row groups (workgroups per strip) */
+  int32_t reserved;    /* must be 0 */
 } drot_params;
 
 typedef struct {

@@ -45,7 +45,7 @@ constexpr size_t kAlign = 256;
 size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Geometry {
-  int vec = 1, chunks = 1;
+  TileCfg tile{1, 1, 4, false};
   SweepGeom g{};
   int n_tiles = 0;
 };
@@ -72,6 +72,10 @@ struct drot_ctx {
   SweepArgs sa{};
   bool finished = false;
 
+  // Iterations enqueued since bind (the skip-C schedule alternates by parity).
+  bool skipc = false;
+  int64_t enq = 0;
+
   // Graph of `check_every` iterations.
   hipGraphExec_t gexec = nullptr;
   int g_iters = 0;
@@ -97,37 +101,57 @@ int choose_geometry(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc,
   const int V = (int)(16 / es);
   const bool aligned = ((uintptr_t)C % 16 == 0) && ((uintptr_t)X % 16 == 0) && (ldc % V == 0) &&
                        (ldx % V == 0) && (n % V == 0);
+  if (p->tile_chunks < 0 || p->tile_chunks > 2)
+    return fail(DROT_EINVAL, "tile_chunks must be 0, 1 or 2 (got %d)", p->tile_chunks);
+  if (p->tile_unroll != 0 && p->tile_unroll != 4 && p->tile_unroll != 8)
+    return fail(DROT_EINVAL, "tile_unroll must be 0, 4 or 8 (got %d)", p->tile_unroll);
+  if (p->cache_mode < DROT_CACHE_AUTO || p->cache_mode > DROT_CACHE_STREAM)
+    return fail(DROT_EINVAL, "unknown cache_mode %d", p->cache_mode);
   Geometry g;
+  const double bytes = 2.0 * (double)m * (double)n * (double)es;
   if (aligned) {
-    g.vec = V;
-    g.chunks = p->tile_chunks > 0 ? p->tile_chunks : 2;
-    if (g.chunks != 1 && g.chunks != 2)
-      return fail(DROT_EINVAL, "tile_chunks must be 0, 1 or 2 (got %d)", p->tile_chunks);
+    // Measured on MI355X: while X and C fit in the last-level cache, cached
+    // accesses with 2 chunks per lane and 32-row blocks; above it, streaming
+    // accesses with 1 chunk per lane and 16-row blocks.
+    g.tile.vec = V;
+    g.tile.stream = p->cache_mode == DROT_CACHE_STREAM ||
+                    (p->cache_mode == DROT_CACHE_AUTO && bytes > 192.0 * 1024 * 1024);
+    g.tile.chunks = p->tile_chunks > 0 ? p->tile_chunks : (g.tile.stream ? 1 : 2);
+    g.tile.unroll = p->tile_unroll > 0 ? p->tile_unroll : 4;
   } else {
-    g.vec = 1;
-    g.chunks = p->tile_chunks == 1 ? 1 : 4;
+    // Scalar path: 4-byte/8-byte accesses, cached, 4 rows in flight.
+    g.tile.vec = 1;
+    g.tile.chunks = p->tile_chunks == 1 ? 1 : 4;
+    g.tile.unroll = 4;
+    g.tile.stream = false;
   }
-  const int64_t W = (int64_t)kWave * g.vec * g.chunks;
+  const int64_t W = (int64_t)kWave * g.tile.vec * g.tile.chunks;
   const int64_t n_ct = (n + W - 1) / W;
   int rows = p->tile_rows;
   if (rows < 0 || rows > 4096) return fail(DROT_EINVAL, "tile_rows must be in [0, 4096]");
+  if (p->tile_groups < 0) return fail(DROT_EINVAL, "tile_groups must be >= 0");
   if (rows == 0) {
-    // Enough tiles to fill 256 CUs several times over, but tall enough to keep
-    // the level-2 column-partial traffic near 1% of the sweep's.
-    rows = 256;
-    while (rows > 16 && ((m + rows - 1) / rows) * n_ct < 1024) rows /= 2;
+    rows = g.tile.stream ? 16 : 32;
+    // Small problems: shorter blocks so that 512+ workgroups share 256 CUs.
+    while (rows > 4 && ((m + rows - 1) / rows) * n_ct < 512) rows /= 2;
   }
   const int64_t n_rb = (m + rows - 1) / rows;
-  if (n_ct * n_rb > 0x7fffffffLL) return fail(DROT_EUNSUPPORTED, "too many tiles");
+  // Row groups (workgroups per strip); by default one row block each, which
+  // measured fastest: many short-lived workgroups keep the streamed band
+  // denser than fewer workgroups walking down their strip.
+  int64_t n_rg = p->tile_groups > 0 ? p->tile_groups : n_rb;
+  n_rg = std::max<int64_t>(1, std::min<int64_t>(n_rg, n_rb));
+  if (n_ct * n_rg > 0x7fffffffLL) return fail(DROT_EUNSUPPORTED, "too many tiles");
   g.g.m = m;
   g.g.n = n;
   g.g.ldc = ldc;
   g.g.ldx = ldx;
   g.g.n_ct = (int)n_ct;
   g.g.n_rb = (int)n_rb;
+  g.g.n_rg = (int)n_rg;
   g.g.rows = rows;
   g.g.ldcp = n_ct * W;
-  g.n_tiles = (int)(n_ct * n_rb);
+  g.n_tiles = (int)(n_ct * n_rg);
   *out = g;
   return DROT_OK;
 }
@@ -150,7 +174,7 @@ int validate(int64_t m, int64_t n, int dtype, const void* C, int64_t ldc, const 
   if (prm->x0_mode != DROT_X0_PQ && prm->x0_mode != DROT_X0_GIVEN)
     return fail(DROT_EINVAL, "unknown x0_mode %d", prm->x0_mode);
   if (prm->check_every < 0) return fail(DROT_EINVAL, "check_every must be >= 0");
-  if (prm->flags & ~(DROT_FLAG_NO_GRAPH | DROT_FLAG_TIME_SWEEP))
+  if (prm->flags & ~(DROT_FLAG_NO_GRAPH | DROT_FLAG_TIME_SWEEP | DROT_FLAG_SKIP_C))
     return fail(DROT_EINVAL, "unknown flags 0x%x", prm->flags);
   if (!C || !p || !q || !X) return fail(DROT_EINVAL, "C, p, q and X must be non-NULL");
   if ((mu0 == nullptr) != (nu0 == nullptr))
@@ -172,7 +196,7 @@ int ensure_workspace(drot_ctx* c, int64_t m, int64_t n, const Geometry& g, size_
   const size_t sizes[12] = {
       sizeof(DevState),
       sizeof(double) * kTraceCap * kTraceWidth,
-      sizeof(double) * (size_t)g.g.n_rb * (size_t)g.g.ldcp,
+      sizeof(double) * (size_t)g.g.n_rg * (size_t)g.g.ldcp,
       sizeof(double) * (size_t)g.g.n_ct * (size_t)m,
       sizeof(double) * (size_t)g.n_tiles * kTileSlots,
       sizeof(double) * (size_t)m,
@@ -204,16 +228,27 @@ int ensure_workspace(drot_ctx* c, int64_t m, int64_t n, const Geometry& g, size_
   return DROT_OK;
 }
 
-int launch_iteration(drot_ctx* c, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+// Sweep mode of the iteration with 0-based index `idx` since bind: plain, or
+// alternating C-reading / C-free under the skip-C schedule.
+int iter_mode(const drot_ctx* c, int64_t idx) {
+  if (!c->skipc) return kIter;
+  return (idx & 1) ? kIterB : kIterA;
+}
+
+int launch_iteration(drot_ctx* c, hipStream_t s, hipEvent_t e0, hipEvent_t e1, int mode) {
   if (e0) HIP_TRY(hipEventRecord(e0, s));
-  HIP_TRY(launch_sweep(c->dtype, kIter, c->geo.vec, c->geo.chunks, c->sa, s));
+  HIP_TRY(launch_sweep(c->dtype, mode, c->geo.tile, c->sa, s));
   if (e1) HIP_TRY(hipEventRecord(e1, s));
-  HIP_TRY(launch_aux(c->dtype, kIter, c->sa, s));
+  HIP_TRY(launch_aux(c->dtype, mode, c->sa, s));
   return DROT_OK;
 }
 
+// Iterations per graph / per host poll (even under the skip-C schedule, so
+// that every graph starts with a C-reading iteration).
 int group_size(const drot_ctx* c) {
-  return c->prm.check_every > 0 ? c->prm.check_every : 32;
+  int g = c->prm.check_every > 0 ? c->prm.check_every : 32;
+  if (c->skipc && (g & 1)) ++g;
+  return g;
 }
 
 int ensure_events(drot_ctx* c, int count) {
@@ -226,10 +261,10 @@ int ensure_events(drot_ctx* c, int count) {
 }
 
 // Capture one launch (the sweep or the aux kernel) into a one-node graph.
-int capture_one(drot_ctx* c, bool sweep, hipGraph_t* out) {
+int capture_one(drot_ctx* c, bool sweep, int mode, hipGraph_t* out) {
   HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-  hipError_t e = sweep ? launch_sweep(c->dtype, kIter, c->geo.vec, c->geo.chunks, c->sa, c->cap_stream)
-                       : launch_aux(c->dtype, kIter, c->sa, c->cap_stream);
+  hipError_t e = sweep ? launch_sweep(c->dtype, mode, c->geo.tile, c->sa, c->cap_stream)
+                       : launch_aux(c->dtype, mode, c->sa, c->cap_stream);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
   if (e != hipSuccess || e2 != hipSuccess) {
@@ -244,22 +279,30 @@ int capture_one(drot_ctx* c, bool sweep, hipGraph_t* out) {
 // sweep (DROT_FLAG_TIME_SWEEP), built node by node; the kernels enter as
 // captured child graphs.
 int build_timed_graph(drot_ctx* c, int G, hipGraph_t* out) {
-  hipGraph_t gs = nullptr, ga = nullptr, g = nullptr;
-  int rc = capture_one(c, true, &gs);
-  if (!rc) rc = capture_one(c, false, &ga);
+  // Child graphs per parity: [0] C-reading (or plain) iteration, [1] C-free.
+  hipGraph_t gs[2] = {nullptr, nullptr}, ga[2] = {nullptr, nullptr}, g = nullptr;
+  const int kinds = c->skipc ? 2 : 1;
+  int rc = DROT_OK;
+  for (int q = 0; q < kinds && !rc; ++q) {
+    rc = capture_one(c, true, iter_mode(c, q), &gs[q]);
+    if (!rc) rc = capture_one(c, false, iter_mode(c, q), &ga[q]);
+  }
   hipError_t e = hipSuccess;
   if (!rc) e = hipGraphCreate(&g, 0);
   hipGraphNode_t prev = nullptr;
   for (int k = 0; k < G && !rc && e == hipSuccess; ++k) {
+    const int q = k % kinds;
     hipGraphNode_t e0, s, e1, x;
     e = hipGraphAddEventRecordNode(&e0, g, prev ? &prev : nullptr, prev ? 1 : 0, c->ev[2 * k]);
-    if (e == hipSuccess) e = hipGraphAddChildGraphNode(&s, g, &e0, 1, gs);
+    if (e == hipSuccess) e = hipGraphAddChildGraphNode(&s, g, &e0, 1, gs[q]);
     if (e == hipSuccess) e = hipGraphAddEventRecordNode(&e1, g, &s, 1, c->ev[2 * k + 1]);
-    if (e == hipSuccess) e = hipGraphAddChildGraphNode(&x, g, &e1, 1, ga);
+    if (e == hipSuccess) e = hipGraphAddChildGraphNode(&x, g, &e1, 1, ga[q]);
     prev = x;
   }
-  if (gs) (void)hipGraphDestroy(gs);
-  if (ga) (void)hipGraphDestroy(ga);
+  for (int q = 0; q < 2; ++q) {
+    if (gs[q]) (void)hipGraphDestroy(gs[q]);
+    if (ga[q]) (void)hipGraphDestroy(ga[q]);
+  }
   if (!rc && e != hipSuccess) rc = fail(DROT_EDEVICE, "timed graph: %s", hipGetErrorString(e));
   if (rc) {
     if (g) (void)hipGraphDestroy(g);
@@ -284,7 +327,7 @@ int ensure_graph(drot_ctx* c) {
     HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     int rc = DROT_OK;
     for (int k = 0; k < G && rc == DROT_OK; ++k)
-      rc = launch_iteration(c, c->cap_stream, nullptr, nullptr);
+      rc = launch_iteration(c, c->cap_stream, nullptr, nullptr, iter_mode(c, k));
     hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
     if (rc != DROT_OK) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -399,6 +442,8 @@ int drot_bind(drot_ctx* c, int64_t m, int64_t n, int dtype, const void* C, int64
   c->dtype = dtype;
   c->prm = *prm;
   c->geo = g;
+  c->skipc = (prm->flags & DROT_FLAG_SKIP_C) != 0;
+  c->enq = 0;
   c->sweep_ms = 0.0;
   c->sweep_n = 0;
   char* base = static_cast<char*>(c->ws);
@@ -440,7 +485,7 @@ int drot_bind(drot_ctx* c, int64_t m, int64_t n, int dtype, const void* C, int64
   HIP_TRY(hipMemcpyAsync(c->st, h, sizeof(DevState), hipMemcpyHostToDevice, s));
   HIP_TRY(launch_prep(sa, s));
   const int mode = prm->x0_mode == DROT_X0_GIVEN ? kInitX : kInitPQ;
-  HIP_TRY(launch_sweep(dtype, mode, g.vec, g.chunks, sa, s));
+  HIP_TRY(launch_sweep(dtype, mode, g.tile, sa, s));
   HIP_TRY(launch_aux(dtype, mode, sa, s));
   HIP_TRY(hipMemcpyAsync(h, c->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -460,57 +505,66 @@ int drot_bind(drot_ctx* c, int64_t m, int64_t n, int dtype, const void* C, int64
   return DROT_OK;
 }
 
-int drot_iterate(drot_ctx* c, int64_t iters, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Enqueue `count` iterations with individual launches (timed in groups when
+// DROT_FLAG_TIME_SWEEP is set).
+int run_eager(drot_ctx* c, hipStream_t s, int64_t count) {
+  const bool timed = (c->prm.flags & DROT_FLAG_TIME_SWEEP) != 0;
+  const int G = group_size(c);
+  int rc = DROT_OK;
+  int64_t done = 0;
+  while (done < count) {
+    const int k = (int)std::min<int64_t>(G, count - done);
+    if (timed && (rc = ensure_events(c, 2 * k))) return rc;
+    for (int t = 0; t < k; ++t) {
+      if ((rc = launch_iteration(c, s, timed ? c->ev[2 * t] : nullptr,
+                                 timed ? c->ev[2 * t + 1] : nullptr, iter_mode(c, c->enq))))
+        return rc;
+      ++c->enq;
+    }
+    if (timed) {
+      HIP_TRY(hipStreamSynchronize(s));
+      if ((rc = harvest_events(c, k))) return rc;
+    }
+    done += k;
+  }
+  return DROT_OK;
+}
+
+}  // namespace
+
+extern "C" int drot_iterate(drot_ctx* c, int64_t iters, void* stream) {
   int rc = check_ctx(c);
   if (rc) return rc;
   if (!c->bound) return fail(DROT_ESTATE, "no problem bound (call drot_bind first)");
   if (iters < 0) return fail(DROT_EINVAL, "iters must be >= 0");
   hipStream_t s = (hipStream_t)stream;
   const bool timed = (c->prm.flags & DROT_FLAG_TIME_SWEEP) != 0;
-  const int G = group_size(c);
   c->finished = false;
-  if (c->prm.flags & DROT_FLAG_NO_GRAPH) {
-    if (timed && (rc = ensure_events(c, 2 * G))) return rc;
-    int64_t done = 0;
-    while (done < iters) {
-      const int k = (int)std::min<int64_t>(G, iters - done);
-      for (int t = 0; t < k; ++t)
-        if ((rc = launch_iteration(c, s, timed ? c->ev[2 * t] : nullptr,
-                                   timed ? c->ev[2 * t + 1] : nullptr)))
-          return rc;
-      if (timed) {
-        HIP_TRY(hipStreamSynchronize(s));
-        if ((rc = harvest_events(c, k))) return rc;
-      }
-      done += k;
-    }
-    return DROT_OK;
-  }
+  if (c->prm.flags & DROT_FLAG_NO_GRAPH) return run_eager(c, s, iters);
   if ((rc = ensure_graph(c))) return rc;
+  const int G = group_size(c);
   int64_t done = 0;
+  if (c->skipc && (c->enq & 1) && iters > 0) {  // realign to a C-reading iteration
+    if ((rc = run_eager(c, s, 1))) return rc;
+    done = 1;
+  }
   while (iters - done >= G) {
     HIP_TRY(hipGraphLaunch(c->gexec, s));
+    c->enq += G;
     if (timed) {
       HIP_TRY(hipStreamSynchronize(s));
       if ((rc = harvest_events(c, G))) return rc;
     }
     done += G;
   }
-  // Remainder eagerly (its timing, if asked for, uses the leading event pairs).
-  const int rest = (int)(iters - done);
-  if (rest > 0) {
-    if (timed && (rc = ensure_events(c, 2 * rest))) return rc;
-    for (int t = 0; t < rest; ++t)
-      if ((rc = launch_iteration(c, s, timed ? c->ev[2 * t] : nullptr,
-                                 timed ? c->ev[2 * t + 1] : nullptr)))
-        return rc;
-    if (timed) {
-      HIP_TRY(hipStreamSynchronize(s));
-      if ((rc = harvest_events(c, rest))) return rc;
-    }
-  }
-  return DROT_OK;
+  return run_eager(c, s, iters - done);
 }
+
+extern "C" {
 
 int drot_poll(drot_ctx* c, int64_t* iters_done, int32_t* stopped, void* stream) {
   int rc = check_ctx(c);
@@ -533,8 +587,13 @@ int drot_finish(drot_ctx* c, double* mu, double* nu, drot_result* out, void* str
   SweepArgs sa = c->sa;
   sa.mu_out = mu;
   sa.nu_out = nu;
-  HIP_TRY(launch_sweep(c->dtype, kFinal, c->geo.vec, c->geo.chunks, sa, s));
-  HIP_TRY(launch_aux(c->dtype, kFinal, sa, s));
+  // Under the skip-C schedule an odd iteration count leaves W = X - rho C in
+  // the array; the final pass then restores X while evaluating it.
+  HIP_TRY(hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const int fmode = (c->skipc && (c->st_host->iter & 1)) ? kFinalW : kFinal;
+  HIP_TRY(launch_sweep(c->dtype, fmode, c->geo.tile, sa, s));
+  HIP_TRY(launch_aux(c->dtype, fmode, sa, s));
   HIP_TRY(hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   const DevState* h = c->st_host;

@@ -14,7 +14,7 @@ constexpr int kTileSlots = 2;      // per-tile scalar partials (see TileSlot)
 constexpr int kSlots = 13;         // per-finisher scalar partials (see Slot)
 constexpr int kTraceCap = 65536;   // per-iteration records kept on the device
 constexpr int kTraceWidth = 8;
-constexpr int kAuxCols = 64;       // columns per aux workgroup
+constexpr int kAuxCols = 32;       // columns per aux workgroup
 
 // Workgroups of one aux launch: column groups of kAuxCols, then rows by kBlock.
 inline int64_t aux_workgroups(int64_t m, int64_t n) {
@@ -27,6 +27,10 @@ enum SweepMode : int {
   kInitPQ = 1,  // steps 1-2 with X_0 = p q^T written; |C|_F; finiteness checks
   kInitX = 2,   // steps 1-2 with X_0 given (read only)
   kFinal = 3,   // read-only FP64 evaluation of (X, phi, psi); writes mu, nu
+  // The paper's skip-C schedule (Claim 1): iterations alternate between
+  kIterA = 4,   // reads X and C, stores W = X_{k+1} - rho C (stopping test as kIter)
+  kIterB = 5,   // reads W only: X_{k+2} = [W + phi e^T + f psi^T]_+ (no test)
+  kFinalW = 6,  // restores X = W + rho C and evaluates like kFinal
 };
 
 // Per-tile scalars: iteration/final: <C,X> and sum [t]_+^2; init: |C|^2 and
@@ -83,8 +87,9 @@ struct SweepGeom {
   int64_t ldc, ldx;
   int64_t ldcp;     // row stride of colpart (n rounded up to a multiple of 4)
   int n_ct;         // column strips
-  int n_rb;         // row blocks
-  int rows;         // rows per workgroup tile
+  int n_rb;         // row blocks of `rows` rows
+  int n_rg;         // row groups: workgroup (strip, g) sweeps row blocks g, g + n_rg, ...
+  int rows;         // rows per row block
 };
 
 struct SweepArgs {
@@ -103,18 +108,26 @@ struct SweepArgs {
   double* mu_out;          // final only, may be null
   double* nu_out;
   DevState* st;
-  void* colpart;           // [n_rb][ldcp] (float in the FP32 iteration, else double)
+  void* colpart;           // [n_rg][ldcp] (float in the FP32 iteration, else double)
   void* rowpart;           // [n_ct][m]
-  double* tiles;           // [n_rb * n_ct][kTileSlots], tile (rb, ct) at rb * n_ct + ct
+  double* tiles;           // [n_rg * n_ct][kTileSlots], workgroup (g, ct) at g * n_ct + ct
   double* blockpart;       // [aux workgroups][kSlots]
   double* trace;           // [kTraceCap][kTraceWidth]
   double wall_rate;        // wall_clock64 ticks per second
   SweepGeom g;
 };
 
-// Launchers (drot_kernels.hip).  `vec` is 4 (float) / 2 (double) for 16-byte
-// loads or 1 for the scalar fallback; `chunks` the chunks per lane.
-hipError_t launch_sweep(int dtype, int mode, int vec, int chunks, const SweepArgs& a,
+// Tile variant of the sweep: `vec` is 4 (float) / 2 (double) for 16-byte
+// loads or 1 for the scalar fallback; `chunks` the chunks per lane (1/2, or
+// 1/4 on the scalar path); `unroll` the rows kept in flight (4 or 8);
+// `stream` selects nontemporal loads and stores.
+struct TileCfg {
+  int vec, chunks, unroll;
+  bool stream;
+};
+
+// Launchers (drot_kernels.hip).
+hipError_t launch_sweep(int dtype, int mode, const TileCfg& t, const SweepArgs& a,
                         hipStream_t s);
 hipError_t launch_aux(int dtype, int mode, const SweepArgs& a, hipStream_t s);
 hipError_t launch_prep(const SweepArgs& a, hipStream_t s);

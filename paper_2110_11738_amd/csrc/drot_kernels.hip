@@ -90,14 +90,26 @@ __device__ __forceinline__ V wave_sum(V v) {
 // ---------------------------------------------------------------------------
 // Types and memory helpers.
 // ---------------------------------------------------------------------------
+// Partial sums of the float32 iteration are float32 (per tile); everything
+// else accumulates in float64.
+constexpr bool is_iter(int mode) { return mode == kIter || mode == kIterA || mode == kIterB; }
+constexpr bool is_final(int mode) { return mode == kFinal || mode == kFinalW; }
+constexpr bool is_init(int mode) { return mode == kInitPQ || mode == kInitX; }
+
 template <typename T, int MODE>
 struct PartialOf {
-  using type = double;
+  using type = typename std::conditional<std::is_same<T, float>::value && is_iter(MODE), float,
+                                         double>::type;
 };
-template <>
-struct PartialOf<float, kIter> {
-  using type = float;
-};
+
+// rho * c rounded once (never fused into a neighbouring add), so that the
+// skip-C schedule's W = X - rho C and its restoration X = W + rho C use the
+// same product and zero entries come back exactly zero.
+template <typename A>
+__device__ __forceinline__ A mul_rounded(A a, A b) {
+#pragma clang fp contract(off)
+  return a * b;
+}
 
 template <typename T, int VEC>
 struct VecOf;
@@ -110,28 +122,34 @@ struct VecOf<double, 2> {
   typedef double type __attribute__((ext_vector_type(2)));
 };
 
-template <typename T, int VEC>
+// 16-byte (or scalar) loads and stores; NT selects the nontemporal
+// (streaming) cache policy, used when the plan and the cost matrix do not fit
+// in the last-level cache.
+template <typename T, int VEC, bool NT>
 __device__ __forceinline__ void load_chunk(const T* ptr, T (&out)[VEC]) {
   if constexpr (VEC == 1) {
-    out[0] = *ptr;
+    out[0] = NT ? __builtin_nontemporal_load(ptr) : *ptr;
   } else {
     using V = typename VecOf<T, VEC>::type;
-    const V v = *reinterpret_cast<const V*>(ptr);
+    const V* vp = reinterpret_cast<const V*>(ptr);
+    const V v = NT ? __builtin_nontemporal_load(vp) : *vp;
 #pragma unroll
     for (int e = 0; e < VEC; ++e) out[e] = v[e];
   }
 }
 
-template <typename T, int VEC>
+template <typename T, int VEC, bool NT>
 __device__ __forceinline__ void store_chunk(T* ptr, const T (&in)[VEC]) {
   if constexpr (VEC == 1) {
-    *ptr = in[0];
+    if (NT) __builtin_nontemporal_store(in[0], ptr);
+    else *ptr = in[0];
   } else {
     using V = typename VecOf<T, VEC>::type;
     V v;
 #pragma unroll
     for (int e = 0; e < VEC; ++e) v[e] = in[e];
-    *reinterpret_cast<V*>(ptr) = v;
+    if (NT) __builtin_nontemporal_store(v, reinterpret_cast<V*>(ptr));
+    else *reinterpret_cast<V*>(ptr) = v;
   }
 }
 
@@ -186,16 +204,19 @@ __device__ void finish_global(const SweepArgs& a, int nb, double (&red)[kSlots][
   const double mn = (double)(m + n);
   const double rho = st->rho;
   const uint64_t now = wall_clock64();
-  if (MODE == kIter) {
+  if (is_iter(MODE)) {
+    // kIterB has no <C,X> and no dual residual (C is not read): it records
+    // NaN for them and can only stop at max_iter.
     const double beta = acc[kSR] / mn;
     const double alpha = st->alpha;
     const double cc = 2.0 * beta - alpha;
     const double cphi = cc / (double)n, cpsi = cc / (double)m;
-    const double pobj = acc[kST0];
+    const double nan = __builtin_nan("");
+    const double pobj = MODE == kIterB ? nan : acc[kST0];
     const double dobj = (acc[kSPphi] + cphi * st->sum_p + acc[kSQpsi] + cpsi * st->sum_q) / rho;
     const double gap = fabs(pobj - dobj);
     const double rp = sqrt(acc[kSR2] + acc[kSS2]);
-    const double rd = sqrt(acc[kST1]) / rho;
+    const double rd = MODE == kIterB ? nan : sqrt(acc[kST1]) / rho;
     const double ep = rp / fmax(st->norm_pq, 1e-300);
     const double ed = rd / fmax(st->norm_c, 1e-300);
     const double eg = gap / fmax(fmax(fabs(pobj), fabs(dobj)), 1e-300);
@@ -222,10 +243,11 @@ __device__ void finish_global(const SweepArgs& a, int nb, double (&red)[kSlots][
     tr[6] = (double)(now - st->t_start) / a.wall_rate;
     tr[7] = (double)k;
     int done = 0, status = 0;
-    if (!finite_d(test) || !finite_d(st->alpha) || !finite_d(cc)) {
+    if ((MODE != kIterB && !finite_d(test)) || !finite_d(st->alpha) || !finite_d(cc) ||
+        !finite_d(rp)) {
       done = 1;
       status = -3;
-    } else if (test <= st->tol) {
+    } else if (MODE != kIterB && test <= st->tol) {
       done = 1;
       status = 0;
     } else if (k >= st->max_iter) {
@@ -238,7 +260,7 @@ __device__ void finish_global(const SweepArgs& a, int nb, double (&red)[kSlots][
       st->stop_iter = k;
       st->t_stop = now;
     }
-  } else if (MODE == kFinal) {
+  } else if (is_final(MODE)) {
     const double pobj = acc[kST0];
     const double dobj = (acc[kSPphi] + acc[kSQpsi]) / rho;
     st->f_pobj = pobj;
@@ -283,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void aux_kernel(SweepArgs a) {
   using V = typename VecOf<P, CW>::type;
 
   DevState* st = a.st;
-  if (MODE == kIter && st->done) return;
+  if (is_iter(MODE) && st->done) return;
 
   __shared__ double red2[G * kAuxCols];
   __shared__ double red[kSlots][kWaves];
@@ -302,14 +324,15 @@ __global__ __launch_bounds__(kBlock) void aux_kernel(SweepArgs a) {
     const int64_t j0 = (int64_t)b * kAuxCols;
     {
       const int ch = threadIdx.x % NCH, grp = threadIdx.x / NCH;
-      const int n_rb = a.g.n_rb;
-      const int r0 = (int)((int64_t)n_rb * grp / G), r1 = (int)((int64_t)n_rb * (grp + 1) / G);
+      const int n_rg = a.g.n_rg;
+      const int r0 = (int)((int64_t)n_rg * grp / G), r1 = (int)((int64_t)n_rg * (grp + 1) / G);
       const P* cp = static_cast<const P*>(a.colpart) + j0 + ch * CW;
       double s[CW];
 #pragma unroll
       for (int e = 0; e < CW; ++e) s[e] = 0.0;
+#pragma unroll 8
       for (int r = r0; r < r1; ++r) {
-        const V v = *reinterpret_cast<const V*>(cp + (int64_t)r * a.g.ldcp);
+        const V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(cp + (int64_t)r * a.g.ldcp));
 #pragma unroll
         for (int e = 0; e < CW; ++e) s[e] += (double)v[e];
       }
@@ -324,7 +347,7 @@ __global__ __launch_bounds__(kBlock) void aux_kernel(SweepArgs a) {
       for (int g = 1; g < G; ++g) v += red2[g * kAuxCols + threadIdx.x];
       const double qj = (double)static_cast<const T*>(a.q)[j];
       const double s = v - qj;
-      if (MODE == kIter) {
+      if (is_iter(MODE)) {
         const double bj = a.b[j];
         const double ps = (bj - 2.0 * s) / (double)m;
         a.b[j] = bj - s;
@@ -333,7 +356,7 @@ __global__ __launch_bounds__(kBlock) void aux_kernel(SweepArgs a) {
         acc[kSS] = s;
         acc[kSS2] = s * s;
         acc[kSQpsi] = qj * ps;
-      } else if (MODE == kFinal) {
+      } else if (is_final(MODE)) {
         const double ps = a.psi64[j] + st->cpsi;
         acc[kSS2] = s * s;
         acc[kSQpsi] = qj * ps;
@@ -359,7 +382,7 @@ __global__ __launch_bounds__(kBlock) void aux_kernel(SweepArgs a) {
       for (int c = 0; c < a.g.n_ct; ++c) u += (double)rp[(int64_t)c * m + i];
       const double pi = (double)static_cast<const T*>(a.p)[i];
       const double r = u - pi;
-      if (MODE == kIter) {
+      if (is_iter(MODE)) {
         const double ai = a.a[i];
         const double ph = (ai - 2.0 * r) / (double)n;
         a.a[i] = ai - r;
@@ -368,7 +391,7 @@ __global__ __launch_bounds__(kBlock) void aux_kernel(SweepArgs a) {
         acc[kSR] = r;
         acc[kSR2] = r * r;
         acc[kSPphi] = pi * ph;
-      } else if (MODE == kFinal) {
+      } else if (is_final(MODE)) {
         const double ph = a.phi64[i] + st->cphi;
         acc[kSR2] = r * r;
         acc[kSPphi] = pi * ph;
@@ -390,7 +413,7 @@ __global__ __launch_bounds__(kBlock) void aux_kernel(SweepArgs a) {
 
   // A fixed slice of the sweep's tile scalars.
   {
-    const int64_t nt = (int64_t)a.g.n_ct * a.g.n_rb;
+    const int64_t nt = (int64_t)a.g.n_ct * a.g.n_rg;
     const int64_t t0 = nt * b / nb, t1 = nt * (b + 1) / nb;
     for (int64_t t = t0 + threadIdx.x; t < t1; t += kBlock) {
       acc[kST0] += a.tiles[t * kTileSlots + kTs0];
@@ -414,33 +437,35 @@ __global__ __launch_bounds__(kBlock) void aux_kernel(SweepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// The sweep.  Tile = `rows` rows x W columns, W = 64 * VEC * CH.  The four
-// waves of a workgroup split the tile's rows into contiguous slices; each
-// lane owns CH chunks of VEC consecutive columns.  Consecutive workgroups
-// take consecutive column strips of the same row block.
+// The sweep.  A workgroup owns one column strip of W = 64 * VEC * CH columns
+// and the row blocks g, g + G, g + 2G, ... of `rows` rows each (G = n_rg row
+// groups): the workgroups running at any moment stream one contiguous band
+// of row blocks (short blocks keep DRAM pages open), while column partials
+// are kept per group, so there are G rows of them instead of one per block.
+// Within a block the four waves take contiguous slices of rows; each lane
+// owns CH chunks of VEC consecutive columns and keeps the loads of U rows in
+// flight.  Consecutive workgroups take consecutive strips of the same group.
 // ---------------------------------------------------------------------------
-template <typename T, int MODE, int VEC, int CH>
+template <typename T, int MODE, int VEC, int CH, int U, bool NT>
 __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a) {
   using P = typename PartialOf<T, MODE>::type;
-  using A = typename std::conditional<MODE == kFinal, double, T>::type;
+  using A = typename std::conditional<is_final(MODE), double, T>::type;
   constexpr int CPL = VEC * CH;
   constexpr int W = kWave * CPL;
-  constexpr int U = 4;
+  constexpr bool kReadC = MODE != kIterB;
+  constexpr bool kReadX = MODE != kInitPQ;
+  constexpr bool kWriteX = MODE != kInitX && MODE != kFinal;
 
   DevState* st = a.st;
-  if (MODE == kIter && st->done) return;
+  if (is_iter(MODE) && st->done) return;
 
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int ct = blockIdx.x % a.g.n_ct;
-  const int rb = blockIdx.x / a.g.n_ct;
+  const int rg = blockIdx.x / a.g.n_ct;
   const int64_t m = a.g.m, n = a.g.n;
   const int64_t col0 = (int64_t)ct * W;
-  const int64_t row0 = (int64_t)rb * a.g.rows;
-  const int64_t rowE = row0 + a.g.rows < m ? row0 + a.g.rows : m;
   const int rpw = (a.g.rows + kWaves - 1) / kWaves;
-  const int64_t rw0 = row0 + (int64_t)wave * rpw;
-  const int64_t rw1 = rw0 + rpw < rowE ? rw0 + rpw : rowE;
 
   const T* __restrict__ C = static_cast<const T*>(a.C);
   T* __restrict__ X = static_cast<T*>(a.X);
@@ -463,17 +488,19 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a) {
       A v = 0;
       if (ok[c]) {
         const int64_t j = jc[c] + e;
-        if (MODE == kIter) v = static_cast<const T*>(a.psiT)[j];
-        if (MODE == kFinal) v = a.psi64[j];
+        if (is_iter(MODE)) v = static_cast<const T*>(a.psiT)[j];
+        if (is_final(MODE)) v = a.psi64[j];
         if (MODE == kInitPQ) v = static_cast<const T*>(a.q)[j];
       }
       colv[c][e] = v;
     }
 
   A shift = 0, rho = 0;
-  if (MODE == kIter || MODE == kFinal) {
+  T rhoT = 0;
+  if (is_iter(MODE) || is_final(MODE)) {
     shift = (A)(st->cphi + st->cpsi);
     rho = (A)st->rho;
+    rhoT = (T)st->rho;
   }
 
   P colacc[CH][VEC];
@@ -485,6 +512,11 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a) {
 
   P* __restrict__ rowpart = static_cast<P*>(a.rowpart);
 
+  for (int64_t rb = rg; rb < a.g.n_rb; rb += a.g.n_rg) {
+  const int64_t row0 = rb * a.g.rows;
+  const int64_t rowE = row0 + a.g.rows < m ? row0 + a.g.rows : m;
+  const int64_t rw0 = row0 + (int64_t)wave * rpw;
+  const int64_t rw1 = rw0 + rpw < rowE ? rw0 + rpw : rowE;
   for (int64_t i0 = rw0; i0 < rw1; i0 += U) {
     T xv[U][CH][VEC], cv[U][CH][VEC];
 #pragma unroll
@@ -494,8 +526,8 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a) {
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
           if (ok[c]) {
-            load_chunk<T, VEC>(C + i * a.g.ldc + jc[c], cv[u][c]);
-            if (MODE != kInitPQ) load_chunk<T, VEC>(X + i * a.g.ldx + jc[c], xv[u][c]);
+            if (kReadC) load_chunk<T, VEC, NT>(C + i * a.g.ldc + jc[c], cv[u][c]);
+            if (kReadX) load_chunk<T, VEC, NT>(X + i * a.g.ldx + jc[c], xv[u][c]);
           }
         }
       }
@@ -505,8 +537,8 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a) {
       const int64_t i = i0 + u;
       if (i < rw1) {
         A rowv = 0;
-        if (MODE == kIter) rowv = static_cast<const T*>(a.phiT)[i] + shift;
-        if (MODE == kFinal) rowv = a.phi64[i] + (double)shift;
+        if (is_iter(MODE)) rowv = static_cast<const T*>(a.phiT)[i] + shift;
+        if (is_final(MODE)) rowv = a.phi64[i] + (double)shift;
         if (MODE == kInitPQ) rowv = static_cast<const T*>(a.p)[i];
         P rsum = 0;
 #pragma unroll
@@ -515,39 +547,54 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a) {
             T outv[VEC];
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
-              const A cij = (A)cv[u][c][e];
               A x;
-              if (MODE == kIter || MODE == kFinal) {
-                const A t = rowv + colv[c][e] - rho * cij;
+              if constexpr (MODE == kIterB) {
+                // X_{k+2} = [W + phi_i + psi_j]_+ with W = X_{k+1} - rho C.
+                const A y = (A)xv[u][c][e] + (rowv + colv[c][e]);
+                x = y > (A)0 ? y : (A)0;
+                outv[e] = (T)x;
+              } else if constexpr (is_iter(MODE) || is_final(MODE)) {
+                const A cij = (A)cv[u][c][e];
+                const A pc = is_final(MODE) ? rho * cij : mul_rounded<A>(rho, cij);
+                const A t = rowv + colv[c][e] - pc;
                 const A tp = t > (A)0 ? t : (A)0;
                 s1 += (P)(tp * tp);
-                if (MODE == kIter) {
+                if constexpr (MODE == kFinalW) {
+                  // Restore X from W in the stored type, with the product the
+                  // C-reading iteration subtracted.
+                  const T pcT = mul_rounded<T>(rhoT, cv[u][c][e]);
+                  const T xr = xv[u][c][e] + pcT;
+                  outv[e] = xr;
+                  x = (A)xr;
+                } else if constexpr (MODE == kFinal) {
+                  x = (A)xv[u][c][e];
+                } else {
                   const A y = (A)xv[u][c][e] + t;
                   x = y > (A)0 ? y : (A)0;
-                } else {
-                  x = (A)xv[u][c][e];
+                  outv[e] = MODE == kIterA ? (T)(x - pc) : (T)x;
                 }
                 s0 += (P)(cij * x);
               } else {
+                const A cij = (A)cv[u][c][e];
                 if (MODE == kInitPQ) x = rowv * colv[c][e];
                 else x = (A)xv[u][c][e];
                 s0 += (P)((double)cij * (double)cij);
                 const bool bad = !finite_d((double)cij) || !finite_d((double)x) ||
                                  (MODE == kInitX && x < (A)0);
                 s1 += bad ? (P)1 : (P)0;
+                outv[e] = (T)x;
               }
-              outv[e] = (T)x;
               rsum += (P)x;
               colacc[c][e] += (P)x;
             }
-            if (MODE == kIter || MODE == kInitPQ)
-              store_chunk<T, VEC>(X + i * a.g.ldx + jc[c], outv);
+            if (kWriteX) store_chunk<T, VEC, NT>(X + i * a.g.ldx + jc[c], outv);
           }
         }
         const P tot = wave_sum(rsum);
         if (lane == 0) rowpart[(int64_t)ct * m + i] = tot;
       }
     }
+  }
   }
 
   // ---- tile partials: combine the four waves in LDS, fixed order -----------
@@ -571,7 +618,7 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a) {
       P v = sm[k];
 #pragma unroll
       for (int w = 1; w < kWaves; ++w) v += sm[w * W + k];
-      colpart[(int64_t)rb * a.g.ldcp + j] = v;
+      colpart[(int64_t)rg * a.g.ldcp + j] = v;
     }
   }
   if (threadIdx.x == 0) {
@@ -581,7 +628,7 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a) {
       v0 += ssc[0][w];
       v1 += ssc[1][w];
     }
-    double* t = a.tiles + ((int64_t)rb * a.g.n_ct + ct) * kTileSlots;
+    double* t = a.tiles + ((int64_t)rg * a.g.n_ct + ct) * kTileSlots;
     t[kTs0] = v0;
     t[kTs1] = v1;
   }
@@ -610,30 +657,55 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(SweepArgs a) {
   }
 }
 
-template <typename T, int MODE, int VEC, int CH>
+template <typename T, int MODE, int VEC, int CH, int U, bool NT>
 hipError_t sweep_go(const SweepArgs& a, hipStream_t s) {
-  const int64_t tiles = (int64_t)a.g.n_ct * a.g.n_rb;
-  hipLaunchKernelGGL((sweep_kernel<T, MODE, VEC, CH>), dim3((unsigned)tiles), dim3(kBlock), 0, s, a);
+  const int64_t tiles = (int64_t)a.g.n_ct * a.g.n_rg;
+  hipLaunchKernelGGL((sweep_kernel<T, MODE, VEC, CH, U, NT>), dim3((unsigned)tiles), dim3(kBlock), 0,
+                     s, a);
   return hipGetLastError();
 }
 
+// The iteration instantiates every tile variant; initialisation and the final
+// evaluation run once per solve and use the plain 4-row, cached variant.
 template <typename T, int MODE>
-hipError_t sweep_mode(int vec, int chunks, const SweepArgs& a, hipStream_t s) {
+hipError_t sweep_mode(const TileCfg& t, const SweepArgs& a, hipStream_t s) {
   constexpr int V = 16 / sizeof(T);
-  if (vec == V && chunks == 1) return sweep_go<T, MODE, V, 1>(a, s);
-  if (vec == V && chunks == 2) return sweep_go<T, MODE, V, 2>(a, s);
-  if (vec == 1 && chunks == 1) return sweep_go<T, MODE, 1, 1>(a, s);
-  if (vec == 1 && chunks == 4) return sweep_go<T, MODE, 1, 4>(a, s);
-  return hipErrorInvalidValue;
+  if (t.vec == 1) {
+    if (t.chunks == 1) return sweep_go<T, MODE, 1, 1, 4, false>(a, s);
+    if (t.chunks == 4) return sweep_go<T, MODE, 1, 4, 4, false>(a, s);
+    return hipErrorInvalidValue;
+  }
+  if (t.vec != V) return hipErrorInvalidValue;
+  if constexpr (is_iter(MODE)) {
+    const int key = (t.chunks == 2 ? 1 : 0) | (t.unroll == 8 ? 2 : 0) | (t.stream ? 4 : 0);
+    switch (key) {
+      case 0: return sweep_go<T, MODE, V, 1, 4, false>(a, s);
+      case 1: return sweep_go<T, MODE, V, 2, 4, false>(a, s);
+      case 2: return sweep_go<T, MODE, V, 1, 8, false>(a, s);
+      case 3: return sweep_go<T, MODE, V, 2, 8, false>(a, s);
+      case 4: return sweep_go<T, MODE, V, 1, 4, true>(a, s);
+      case 5: return sweep_go<T, MODE, V, 2, 4, true>(a, s);
+      case 6: return sweep_go<T, MODE, V, 1, 8, true>(a, s);
+      case 7: return sweep_go<T, MODE, V, 2, 8, true>(a, s);
+    }
+    return hipErrorInvalidValue;
+  } else {
+    if (t.chunks == 1) return sweep_go<T, MODE, V, 1, 4, false>(a, s);
+    if (t.chunks == 2) return sweep_go<T, MODE, V, 2, 4, false>(a, s);
+    return hipErrorInvalidValue;
+  }
 }
 
 template <typename T>
-hipError_t sweep_type(int mode, int vec, int chunks, const SweepArgs& a, hipStream_t s) {
+hipError_t sweep_type(int mode, const TileCfg& t, const SweepArgs& a, hipStream_t s) {
   switch (mode) {
-    case kIter: return sweep_mode<T, kIter>(vec, chunks, a, s);
-    case kInitPQ: return sweep_mode<T, kInitPQ>(vec, chunks, a, s);
-    case kInitX: return sweep_mode<T, kInitX>(vec, chunks, a, s);
-    case kFinal: return sweep_mode<T, kFinal>(vec, chunks, a, s);
+    case kIter: return sweep_mode<T, kIter>(t, a, s);
+    case kInitPQ: return sweep_mode<T, kInitPQ>(t, a, s);
+    case kInitX: return sweep_mode<T, kInitX>(t, a, s);
+    case kFinal: return sweep_mode<T, kFinal>(t, a, s);
+    case kIterA: return sweep_mode<T, kIterA>(t, a, s);
+    case kIterB: return sweep_mode<T, kIterB>(t, a, s);
+    case kFinalW: return sweep_mode<T, kFinalW>(t, a, s);
   }
   return hipErrorInvalidValue;
 }
@@ -642,10 +714,13 @@ template <typename T>
 hipError_t aux_type(int mode, const SweepArgs& a, hipStream_t s) {
   const dim3 grid((unsigned)aux_workgroups(a.g.m, a.g.n));
   switch (mode) {
-    case kIter: hipLaunchKernelGGL((aux_kernel<T, kIter>), grid, dim3(kBlock), 0, s, a); break;
+    case kIter:
+    case kIterA: hipLaunchKernelGGL((aux_kernel<T, kIter>), grid, dim3(kBlock), 0, s, a); break;
+    case kIterB: hipLaunchKernelGGL((aux_kernel<T, kIterB>), grid, dim3(kBlock), 0, s, a); break;
     case kInitPQ:
     case kInitX: hipLaunchKernelGGL((aux_kernel<T, kInitPQ>), grid, dim3(kBlock), 0, s, a); break;
-    case kFinal: hipLaunchKernelGGL((aux_kernel<T, kFinal>), grid, dim3(kBlock), 0, s, a); break;
+    case kFinal:
+    case kFinalW: hipLaunchKernelGGL((aux_kernel<T, kFinal>), grid, dim3(kBlock), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -657,10 +732,9 @@ hipError_t launch_aux(int dtype, int mode, const SweepArgs& a, hipStream_t s) {
   return dtype == 0 ? aux_type<float>(mode, a, s) : aux_type<double>(mode, a, s);
 }
 
-hipError_t launch_sweep(int dtype, int mode, int vec, int chunks, const SweepArgs& a,
+hipError_t launch_sweep(int dtype, int mode, const TileCfg& t, const SweepArgs& a,
                         hipStream_t s) {
-  return dtype == 0 ? sweep_type<float>(mode, vec, chunks, a, s)
-                    : sweep_type<double>(mode, vec, chunks, a, s);
+  return dtype == 0 ? sweep_type<float>(mode, t, a, s) : sweep_type<double>(mode, t, a, s);
 }
 
 hipError_t launch_prep(const SweepArgs& a, hipStream_t s) {

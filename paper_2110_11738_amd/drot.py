@@ -22,7 +22,8 @@ EINVAL, EMASS, ENONFINITE, ENOMEM, EDEVICE, EUNSUPPORTED, ESTATE = -1, -2, -3, -
 F32, F64 = 0, 1
 TOL_RELATIVE, TOL_ABSOLUTE = 0, 1
 X0_PQ, X0_GIVEN = 0, 1
-FLAG_NO_GRAPH, FLAG_TIME_SWEEP = 0x1, 0x2
+FLAG_NO_GRAPH, FLAG_TIME_SWEEP, FLAG_SKIP_C = 0x1, 0x2, 0x4
+CACHE_AUTO, CACHE_CACHED, CACHE_STREAM = 0, 1, 2
 TRACE_FIELDS = ("pobj", "dobj", "r_primal", "r_dual_lag", "gap", "test", "seconds", "k")
 
 EXPORTED = ("drot_version", "drot_strerror", "drot_last_error", "drot_ctx_create",
@@ -35,7 +36,9 @@ class Params(ctypes.Structure):
                 ("max_iter", ctypes.c_int64), ("tol_mode", ctypes.c_int32),
                 ("x0_mode", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
-                ("tile_chunks", ctypes.c_int32)]
+                ("tile_chunks", ctypes.c_int32), ("tile_unroll", ctypes.c_int32),
+                ("cache_mode", ctypes.c_int32), ("tile_groups", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -126,9 +129,11 @@ def _ld(t) -> int:
 
 
 def make_params(rho, tol=0.0, max_iter=100000, tol_mode=TOL_RELATIVE, x0_mode=X0_PQ,
-                check_every=0, flags=0, tile_rows=0, tile_chunks=0) -> Params:
+                check_every=0, flags=0, tile_rows=0, tile_chunks=0, tile_unroll=0,
+                cache_mode=CACHE_AUTO, tile_groups=0) -> Params:
     return Params(float(rho), float(tol), int(max_iter), int(tol_mode), int(x0_mode),
-                  int(check_every), int(flags), int(tile_rows), int(tile_chunks))
+                  int(check_every), int(flags), int(tile_rows), int(tile_chunks),
+                  int(tile_unroll), int(cache_mode), int(tile_groups), 0)
 
 
 class Context:
@@ -218,7 +223,8 @@ class Solution:
 
 def solve(C, p, q, rho: float, tol: float = 1e-4, max_iter: int = 100000,
           tol_mode: int = TOL_RELATIVE, X0=None, mu0=None, nu0=None, check_every: int = 0,
-          flags: int = 0, tile_rows: int = 0, tile_chunks: int = 0, ctx: Context | None = None,
+          flags: int = 0, tile_rows: int = 0, tile_chunks: int = 0, tile_unroll: int = 0,
+          cache_mode: int = CACHE_AUTO, tile_groups: int = 0, ctx: Context | None = None,
           stream=None):
     """solve(C, p, q, rho, tol) -> (X, result, mu, nu) on C's device.
 
@@ -235,6 +241,7 @@ def solve(C, p, q, rho: float, tol: float = 1e-4, max_iter: int = 100000,
     mu = torch.empty(m, dtype=torch.float64, device=C.device)
     nu = torch.empty(n, dtype=torch.float64, device=C.device)
     prm = make_params(rho, tol, max_iter, tol_mode, X0_PQ if X0 is None else X0_GIVEN,
-                      check_every, flags, tile_rows, tile_chunks)
+                      check_every, flags, tile_rows, tile_chunks, tile_unroll, cache_mode,
+                      tile_groups)
     X, res = ctx.solve(C, p, q, prm, X=X, mu=mu, nu=nu, mu0=mu0, nu0=nu0, stream=stream)
     return X, res, mu, nu

@@ -259,3 +259,79 @@ def test_timed_sweeps_change_nothing(ctx, flags):
     np.testing.assert_array_equal(base[2], timed[2])
     assert timed[1]["sweep_timed"] == 80
     assert timed[1]["sweep_ms_total"] > 0
+
+
+@pytest.mark.parametrize("cache_mode,unroll,chunks", [(2, 8, 2), (2, 4, 1), (1, 8, 1), (1, 4, 2)])
+def test_tile_variants_agree_with_oracle(ctx, cache_mode, unroll, chunks):
+    """Streaming/cached accesses and 4/8-row unrolling change only the
+    schedule: every variant matches the oracle, and rows not divisible by the
+    unroll depth are covered (37 rows per tile)."""
+    inst = round_to(config_mixture_2d(11, 517, 1024), np.float32)
+    Xg, res, mu, nu = _run(ctx, inst, "float32", 12, tile_rows=37, tile_chunks=chunks,
+                           tile_unroll=unroll, cache_mode=cache_mode)
+    R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=12)
+    assert _rel_max(Xg, R.X) <= TOL["float32"][0]
+    assert _rel_max(mu, R.mu) <= TOL["float32"][1]
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_skip_c_schedule_trajectory(ctx, dtype):
+    """The paper's skip-C schedule (Claim 1) is the same iteration with C read
+    on every other step: after K steps (odd K ends on a C-reading step and
+    makes the final pass restore X from W = X - rho C) it matches the oracle."""
+    from paper_2110_11738_amd import drot
+    inst = _rounded(config_mixture_2d(12, 300, 516), dtype)
+    tx, td, to = TOL[dtype]
+    for K in (1, 2, 7, 30):
+        Xg, res, mu, nu = _run(ctx, inst, dtype, K, flags=drot.FLAG_SKIP_C, check_every=8)
+        R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=K)
+        ex, emu = _rel_max(Xg, R.X), _rel_max(mu, R.mu)
+        print(f"[skip-C] {dtype} K={K}: X {ex:.2e} mu {emu:.2e}", flush=True)
+        assert res["iters"] == K
+        assert Xg.min() >= 0.0
+        assert ex <= tx and emu <= td
+        assert abs(res["objective"] - R.info["pobj"]) <= to * abs(R.info["pobj"])
+
+
+def test_skip_c_graph_eager_and_stop(ctx):
+    from paper_2110_11738_amd import drot
+    inst = round_to(config_mixture_2d(13, 200, 256), np.float32)
+    a = _run(ctx, inst, "float32", 41, flags=drot.FLAG_SKIP_C, check_every=7)
+    b = _run(ctx, inst, "float32", 41, flags=drot.FLAG_SKIP_C | drot.FLAG_NO_GRAPH)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[2], b[2])
+    # float32 solve to tolerance: same answer as the plain schedule
+    Xs, rs, mus, nus = _run(ctx, inst, "float32", 1_000_000, tol=1e-4, flags=drot.FLAG_SKIP_C)
+    Xp, rp, mup, nup = _run(ctx, inst, "float32", 1_000_000, tol=1e-4)
+    print(f"[skip-C] fp32 stop at {rs['iters']} vs plain {rp['iters']}", flush=True)
+    assert rs["status"] == 0 and rs["iters"] % 2 == 1
+    assert abs(rs["objective"] - rp["objective"]) <= 1e-4 * rp["objective"]
+    assert rs["eps_primal"] <= 1e-4 and Xs.min() >= 0.0
+
+
+def test_skip_c_stops_at_first_odd_passing_iteration():
+    """In float64 the schedule follows the oracle's trajectory, so it must stop
+    at the first C-reading (odd) iteration whose stopping-test value, taken
+    from the oracle's trace, is at most tol."""
+    from paper_2110_11738_amd import drot
+    c = drot.Context(0)
+    inst = config_small_fp64(0)
+    Xg, res, mu, nu = _run(c, inst, "float64", 2_000_000, tol=inst.tol, flags=drot.FLAG_SKIP_C)
+    R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=res["iters"] + 3, trace=True)
+    test = R.trace[:, 5]
+    odd = [k for k in range(1, len(test) + 1, 2) if test[k - 1] <= inst.tol]
+    print(f"[skip-C] fp64 stop at {res['iters']}, oracle first odd pass {odd[:1]}", flush=True)
+    assert res["status"] == 0 and odd and res["iters"] == odd[0]
+    c.close()
+
+
+@pytest.mark.parametrize("rows,groups", [(16, 1), (16, 3), (8, 7), (5, 64)])
+def test_row_groups_agree_with_oracle(ctx, rows, groups):
+    """Workgroups sweeping every `groups`-th row block of their strip (ragged
+    last block, more groups than blocks) give the oracle's iterates."""
+    inst = round_to(config_mixture_2d(14, 333, 1024), np.float32)
+    Xg, res, mu, nu = _run(ctx, inst, "float32", 9, tile_rows=rows, tile_groups=groups)
+    R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=9)
+    assert _rel_max(Xg, R.X) <= TOL["float32"][0]
+    assert _rel_max(mu, R.mu) <= TOL["float32"][1]
+    assert abs(res["objective"] - R.info["pobj"]) <= TOL["float32"][2] * R.info["pobj"]

@@ -43,9 +43,9 @@ def test_binding_covers_every_export():
 
 def test_struct_layouts_match_header(lib):
     from paper_2110_11738_amd import drot
-    # drot_params: 2 doubles, 1 int64, 6 int32 -> 48 bytes;
+    # drot_params: 2 doubles, 1 int64, 10 int32 -> 64 bytes;
     # drot_result: int64, 2 int32, 11 doubles, int64 -> 112 bytes
-    assert ctypes.sizeof(drot.Params) == 48
+    assert ctypes.sizeof(drot.Params) == 64
     assert ctypes.sizeof(drot.Result) == 112
 
 
