@@ -133,6 +133,8 @@ def main():
     ap.add_argument("--tile-unroll", type=int, default=0)
     ap.add_argument("--cache-mode", type=int, default=0, help="0 auto, 1 cached, 2 streaming")
     ap.add_argument("--tile-groups", type=int, default=0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (counter calibration for profiles)")
     ap.add_argument("--check-every", type=int, default=64)
     args = ap.parse_args()
 
@@ -229,6 +231,17 @@ def main():
                                      "launches_timed": cnt_l}}
         log(f"{L}^2: {ksteps / secs_l:.1f} it/s, sweep {sweep_l * 1e3:.1f} us -> {ach:.0f} GB/s "
             f"({100 * ach / HBM_PEAK_GBS:.1f}% of peak)")
+
+    if args.calibrate_copy:
+        # A plain copy of known size: under `rocprofv3 --pmc FETCH_SIZE` (or
+        # WRITE_SIZE) its counters give the factor that converts the sweep's
+        # counters into bytes.
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = src.numel() * 4
 
     ctx.close()
     print(json.dumps(out), flush=True)

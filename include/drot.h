@@ -127,7 +127,30 @@ typedef struct {
   double sweep_ms_total;  /* with DROT_FLAG_TIME_SWEEP: summed hipEvent time of
                              the timed sweep launches, else 0 */
   int64_t sweep_timed;    /* number of sweep launches in sweep_ms_total */
+  double cost_scale;      /* DROT_COST_COORDS: the scale used (given or computed), else 0 */
 } drot_result;
+
+/* Where the sweep takes the cost c_ij from.  The paper's problem allows any
+ * nonnegative m x n cost (eq. 1); its experiments use squared Euclidean
+ * distances between point clouds, normalised to max 1 (Section 4).  Reading
+ * fewer bytes per entry is the main lever of a bandwidth-bound sweep:
+ *   DROT_COST_DENSE   C stored in the problem dtype (12 B/entry/iteration in float32)
+ *   DROT_COST_BF16    C stored as bfloat16 bit patterns, float32 problems only
+ *                     (10 B/entry); c_ij is the bfloat16 value widened exactly
+ *   DROT_COST_COORDS  c_ij = scale * sum_d (xs_id - xt_jd)^2 evaluated in float32
+ *                     from float32 coordinates, float32 problems only (8 B/entry) */
+typedef enum { DROT_COST_DENSE = 0, DROT_COST_BF16 = 1, DROT_COST_COORDS = 2 } drot_cost_kind;
+
+typedef struct {
+  int32_t kind;       /* drot_cost_kind */
+  int32_t dim;        /* COORDS: point dimension d, 1..3 */
+  const void *data;   /* DENSE: C (problem dtype); BF16: C as uint16_t bfloat16 patterns */
+  int64_t ld;         /* DENSE, BF16: leading dimension in elements, >= n */
+  const float *xs;    /* COORDS: source points, m x d, row-major */
+  const float *xt;    /* COORDS: target points, n x d, row-major */
+  double scale;       /* COORDS: > 0 the scale; 0 = 1 / max_ij |xs_i - xt_j|^2, computed
+                         on the device (reported in drot_result.cost_scale) */
+} drot_cost;
 
 /* ---- library and context -------------------------------------------- */
 
@@ -196,6 +219,17 @@ int drot_poll(drot_ctx *ctx, int64_t *iters_done, int32_t *stopped, void *stream
  * (X, mu, nu), accumulated in FP64; writes mu and nu if non-NULL and fills
  * `out`.  Blocks until done. */
 int drot_finish(drot_ctx *ctx, double *mu, double *nu, drot_result *out, void *stream);
+
+/* drot_bind / drot_solve with a cost descriptor instead of a dense C
+ * (arguments otherwise as above).  The skip-C schedule needs a dense C. */
+int drot_bind_cost(drot_ctx *ctx, int64_t m, int64_t n, int dtype, const drot_cost *cost,
+                   const void *p, const void *q, const drot_params *params, void *X,
+                   int64_t ldx, const double *mu0, const double *nu0, void *stream);
+
+int drot_solve_cost(drot_ctx *ctx, int64_t m, int64_t n, int dtype, const drot_cost *cost,
+                    const void *p, const void *q, const drot_params *params, void *X,
+                    int64_t ldx, double *mu, double *nu, const double *mu0, const double *nu0,
+                    drot_result *out, void *stream);
 
 /* Copy per-iteration records of the last bound problem to host memory.
  * Record k (1-based iteration index) holds 8 doubles:

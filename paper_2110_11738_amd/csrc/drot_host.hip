@@ -45,7 +45,7 @@ constexpr size_t kAlign = 256;
 size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Geometry {
-  TileCfg tile{1, 1, 4, false};
+  TileCfg tile{1, 1, 4, false, false};
   SweepGeom g{};
   int n_tiles = 0;
 };
@@ -95,12 +95,17 @@ void drop_graph(drot_ctx* c) {
   c->g_iters = 0;
 }
 
-int choose_geometry(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc, const void* X,
+int choose_geometry(int dtype, int64_t m, int64_t n, const drot_cost* cost, const void* X,
                     int64_t ldx, const drot_params* p, Geometry* out) {
   const size_t es = dtype == DROT_F32 ? 4 : 8;
   const int V = (int)(16 / es);
-  const bool aligned = ((uintptr_t)C % 16 == 0) && ((uintptr_t)X % 16 == 0) && (ldc % V == 0) &&
-                       (ldx % V == 0) && (n % V == 0);
+  // 16-byte path: X (and a dense C) 16-byte aligned with leading dimensions
+  // that are multiples of the vector width; n itself may be ragged.
+  bool aligned = ((uintptr_t)X % 16 == 0) && (ldx % V == 0);
+  if (cost->kind == DROT_COST_DENSE)
+    aligned = aligned && ((uintptr_t)cost->data % 16 == 0) && (cost->ld % V == 0);
+  if (cost->kind == DROT_COST_BF16)
+    aligned = aligned && ((uintptr_t)cost->data % 8 == 0) && (cost->ld % V == 0);
   if (p->tile_chunks < 0 || p->tile_chunks > 2)
     return fail(DROT_EINVAL, "tile_chunks must be 0, 1 or 2 (got %d)", p->tile_chunks);
   if (p->tile_unroll != 0 && p->tile_unroll != 4 && p->tile_unroll != 8)
@@ -108,7 +113,9 @@ int choose_geometry(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc,
   if (p->cache_mode < DROT_CACHE_AUTO || p->cache_mode > DROT_CACHE_STREAM)
     return fail(DROT_EINVAL, "unknown cache_mode %d", p->cache_mode);
   Geometry g;
-  const double bytes = 2.0 * (double)m * (double)n * (double)es;
+  const double cbytes = cost->kind == DROT_COST_DENSE ? (double)es
+                        : cost->kind == DROT_COST_BF16 ? 2.0 : 0.0;
+  const double bytes = (double)m * (double)n * ((double)es + cbytes);
   if (aligned) {
     // Measured on MI355X: while X and C fit in the last-level cache, cached
     // accesses with 2 chunks per lane and 32-row blocks; above it, streaming
@@ -118,6 +125,8 @@ int choose_geometry(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc,
                     (p->cache_mode == DROT_CACHE_AUTO && bytes > 192.0 * 1024 * 1024);
     g.tile.chunks = p->tile_chunks > 0 ? p->tile_chunks : (g.tile.stream ? 1 : 2);
     g.tile.unroll = p->tile_unroll > 0 ? p->tile_unroll : 4;
+    g.tile.ragged = n % V != 0;
+    if (g.tile.ragged) g.tile.unroll = 4;
   } else {
     // Scalar path: 4-byte/8-byte accesses, cached, 4 rows in flight.
     g.tile.vec = 1;
@@ -144,7 +153,7 @@ int choose_geometry(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc,
   if (n_ct * n_rg > 0x7fffffffLL) return fail(DROT_EUNSUPPORTED, "too many tiles");
   g.g.m = m;
   g.g.n = n;
-  g.g.ldc = ldc;
+  g.g.ldc = cost->kind == DROT_COST_COORDS ? 0 : cost->ld;
   g.g.ldx = ldx;
   g.g.n_ct = (int)n_ct;
   g.g.n_rb = (int)n_rb;
@@ -156,13 +165,18 @@ int choose_geometry(int dtype, int64_t m, int64_t n, const void* C, int64_t ldc,
   return DROT_OK;
 }
 
-int validate(int64_t m, int64_t n, int dtype, const void* C, int64_t ldc, const void* p,
+int validate(int64_t m, int64_t n, int dtype, const drot_cost* cost, const void* p,
              const void* q, const drot_params* prm, void* X, int64_t ldx, const double* mu0,
              const double* nu0) {
   if (m < 1 || n < 1) return fail(DROT_EINVAL, "m and n must be >= 1 (got %lld, %lld)",
                                   (long long)m, (long long)n);
   if (dtype != DROT_F32 && dtype != DROT_F64) return fail(DROT_EINVAL, "unknown dtype %d", dtype);
-  if (ldc < n || ldx < n) return fail(DROT_EINVAL, "leading dimensions must be >= n");
+  if (!cost) return fail(DROT_EINVAL, "cost descriptor is NULL");
+  if (cost->kind < DROT_COST_DENSE || cost->kind > DROT_COST_COORDS)
+    return fail(DROT_EINVAL, "unknown cost kind %d", cost->kind);
+  if (cost->kind != DROT_COST_COORDS && cost->ld < n)
+    return fail(DROT_EINVAL, "leading dimensions must be >= n");
+  if (ldx < n) return fail(DROT_EINVAL, "leading dimensions must be >= n");
   if (!prm) return fail(DROT_EINVAL, "params is NULL");
   if (!(prm->rho > 0) || !std::isfinite(prm->rho))
     return fail(DROT_EINVAL, "rho must be positive and finite");
@@ -176,16 +190,35 @@ int validate(int64_t m, int64_t n, int dtype, const void* C, int64_t ldc, const 
   if (prm->check_every < 0) return fail(DROT_EINVAL, "check_every must be >= 0");
   if (prm->flags & ~(DROT_FLAG_NO_GRAPH | DROT_FLAG_TIME_SWEEP | DROT_FLAG_SKIP_C))
     return fail(DROT_EINVAL, "unknown flags 0x%x", prm->flags);
-  if (!C || !p || !q || !X) return fail(DROT_EINVAL, "C, p, q and X must be non-NULL");
+  if (cost->kind != DROT_COST_DENSE && dtype != DROT_F32)
+    return fail(DROT_EUNSUPPORTED, "bfloat16 and coordinate costs need a float32 problem");
+  if (cost->kind != DROT_COST_DENSE && (prm->flags & DROT_FLAG_SKIP_C))
+    return fail(DROT_EUNSUPPORTED, "the skip-C schedule needs a dense cost matrix");
+  if (cost->kind == DROT_COST_COORDS) {
+    if (cost->dim < 1 || cost->dim > 3) return fail(DROT_EINVAL, "coordinate dimension must be 1..3");
+    if (!cost->xs || !cost->xt) return fail(DROT_EINVAL, "xs and xt must be non-NULL");
+    if ((uintptr_t)cost->xs % 4 || (uintptr_t)cost->xt % 4)
+      return fail(DROT_EINVAL, "coordinates must be 4-byte aligned");
+    if (!(cost->scale >= 0) || !std::isfinite(cost->scale))
+      return fail(DROT_EINVAL, "scale must be >= 0 and finite");
+  } else if (!cost->data) {
+    return fail(DROT_EINVAL, "C must be non-NULL");
+  }
+  const void* C = cost->kind == DROT_COST_COORDS ? nullptr : cost->data;
+  const int64_t ldc = cost->ld;
+  if (!p || !q || !X) return fail(DROT_EINVAL, "C, p, q and X must be non-NULL");
   if ((mu0 == nullptr) != (nu0 == nullptr))
     return fail(DROT_EINVAL, "mu0 and nu0 must be given together");
   const size_t es = dtype == DROT_F32 ? 4 : 8;
-  if ((uintptr_t)C % es || (uintptr_t)X % es || (uintptr_t)p % es || (uintptr_t)q % es)
+  const size_t ces = cost->kind == DROT_COST_BF16 ? 2 : es;
+  if ((C && (uintptr_t)C % ces) || (uintptr_t)X % es || (uintptr_t)p % es || (uintptr_t)q % es)
     return fail(DROT_EINVAL, "arrays must be aligned to their element size");
-  // Overlap of C and X (both m x n with their leading dimensions).
-  const uintptr_t c0 = (uintptr_t)C, c1 = c0 + (size_t)((m - 1) * ldc + n) * es;
-  const uintptr_t x0 = (uintptr_t)X, x1 = x0 + (size_t)((m - 1) * ldx + n) * es;
-  if (c0 < x1 && x0 < c1) return fail(DROT_EINVAL, "C and X overlap");
+  if (C) {
+    // Overlap of C and X (both m x n with their leading dimensions).
+    const uintptr_t c0 = (uintptr_t)C, c1 = c0 + (size_t)((m - 1) * ldc + n) * ces;
+    const uintptr_t x0 = (uintptr_t)X, x1 = x0 + (size_t)((m - 1) * ldx + n) * es;
+    if (c0 < x1 && x0 < c1) return fail(DROT_EINVAL, "C and X overlap");
+  }
   return DROT_OK;
 }
 
@@ -425,14 +458,14 @@ int drot_ctx_destroy(drot_ctx* c) {
   return DROT_OK;
 }
 
-int drot_bind(drot_ctx* c, int64_t m, int64_t n, int dtype, const void* C, int64_t ldc,
-              const void* p, const void* q, const drot_params* prm, void* X, int64_t ldx,
-              const double* mu0, const double* nu0, void* stream) {
-  int rc = validate(m, n, dtype, C, ldc, p, q, prm, X, ldx, mu0, nu0);
+int drot_bind_cost(drot_ctx* c, int64_t m, int64_t n, int dtype, const drot_cost* cost,
+                   const void* p, const void* q, const drot_params* prm, void* X, int64_t ldx,
+                   const double* mu0, const double* nu0, void* stream) {
+  int rc = validate(m, n, dtype, cost, p, q, prm, X, ldx, mu0, nu0);
   if (rc) return rc;
   if ((rc = check_ctx(c))) return rc;
   Geometry g;
-  if ((rc = choose_geometry(dtype, m, n, C, ldc, X, ldx, prm, &g))) return rc;
+  if ((rc = choose_geometry(dtype, m, n, cost, X, ldx, prm, &g))) return rc;
   size_t offs[12];
   if ((rc = ensure_workspace(c, m, n, g, offs))) return rc;
   hipStream_t s = (hipStream_t)stream;
@@ -452,7 +485,11 @@ int drot_bind(drot_ctx* c, int64_t m, int64_t n, int dtype, const void* C, int64
 
   SweepArgs& sa = c->sa;
   sa = SweepArgs{};
-  sa.C = C;
+  sa.cost_kind = cost->kind;
+  sa.dim = cost->dim;
+  sa.xs = cost->xs;
+  sa.xt = cost->xt;
+  sa.C = cost->kind == DROT_COST_COORDS ? nullptr : cost->data;
   sa.X = X;
   sa.p = p;
   sa.q = q;
@@ -482,7 +519,9 @@ int drot_bind(drot_ctx* c, int64_t m, int64_t n, int dtype, const void* C, int64
   h->tol_mode = prm->tol_mode;
   h->m = m;
   h->n = n;
+  h->cscale = cost->kind == DROT_COST_COORDS ? cost->scale : 0.0;
   HIP_TRY(hipMemcpyAsync(c->st, h, sizeof(DevState), hipMemcpyHostToDevice, s));
+  if (cost->kind == DROT_COST_COORDS && !(cost->scale > 0)) HIP_TRY(launch_maxc(sa, s));
   HIP_TRY(launch_prep(sa, s));
   const int mode = prm->x0_mode == DROT_X0_GIVEN ? kInitX : kInitPQ;
   HIP_TRY(launch_sweep(dtype, mode, g.tile, sa, s));
@@ -503,6 +542,16 @@ int drot_bind(drot_ctx* c, int64_t m, int64_t n, int dtype, const void* C, int64
     return fail(DROT_EMASS, "sum(p) = %.17g and sum(q) = %.17g differ (or are not positive)", sp, sq);
   c->bound = true;
   return DROT_OK;
+}
+
+int drot_bind(drot_ctx* c, int64_t m, int64_t n, int dtype, const void* C, int64_t ldc,
+              const void* p, const void* q, const drot_params* prm, void* X, int64_t ldx,
+              const double* mu0, const double* nu0, void* stream) {
+  drot_cost cost{};
+  cost.kind = DROT_COST_DENSE;
+  cost.data = C;
+  cost.ld = ldc;
+  return drot_bind_cost(c, m, n, dtype, &cost, p, q, prm, X, ldx, mu0, nu0, stream);
 }
 
 }  // extern "C"
@@ -612,6 +661,7 @@ int drot_finish(drot_ctx* c, double* mu, double* nu, drot_result* out, void* str
   out->seconds_to_tol = (double)(t1 - h->t_start) / c->wall_rate;
   out->sweep_ms_total = c->sweep_ms;
   out->sweep_timed = c->sweep_n;
+  out->cost_scale = c->sa.cost_kind == kCostCoords ? h->cscale : 0.0;
   c->finished = true;
   if (out->status == -3)
     return fail(DROT_ENONFINITE, "the iteration produced a non-finite value at iteration %lld",
@@ -638,15 +688,15 @@ int drot_get_trace(drot_ctx* c, int64_t first, int64_t count, double* host_out) 
   return DROT_OK;
 }
 
-int drot_solve(drot_ctx* c, int64_t m, int64_t n, int dtype, const void* C, int64_t ldc,
-               const void* p, const void* q, const drot_params* prm, void* X, int64_t ldx,
-               double* mu, double* nu, const double* mu0, const double* nu0, drot_result* out,
-               void* stream) {
+int drot_solve_cost(drot_ctx* c, int64_t m, int64_t n, int dtype, const drot_cost* cost,
+                    const void* p, const void* q, const drot_params* prm, void* X, int64_t ldx,
+                    double* mu, double* nu, const double* mu0, const double* nu0,
+                    drot_result* out, void* stream) {
   const auto t0 = std::chrono::steady_clock::now();
   if (!out) return fail(DROT_EINVAL, "out is NULL");
-  int rc = validate(m, n, dtype, C, ldc, p, q, prm, X, ldx, mu0, nu0);
+  int rc = validate(m, n, dtype, cost, p, q, prm, X, ldx, mu0, nu0);
   if (rc) return rc;
-  if ((rc = drot_bind(c, m, n, dtype, C, ldc, p, q, prm, X, ldx, mu0, nu0, stream))) return rc;
+  if ((rc = drot_bind_cost(c, m, n, dtype, cost, p, q, prm, X, ldx, mu0, nu0, stream))) return rc;
   const int G = group_size(c);
   int64_t done_iters = 0;
   int32_t stopped = 0;
@@ -659,6 +709,17 @@ int drot_solve(drot_ctx* c, int64_t m, int64_t n, int dtype, const void* C, int6
   out->seconds_total =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return rc;
+}
+
+int drot_solve(drot_ctx* c, int64_t m, int64_t n, int dtype, const void* C, int64_t ldc,
+               const void* p, const void* q, const drot_params* prm, void* X, int64_t ldx,
+               double* mu, double* nu, const double* mu0, const double* nu0, drot_result* out,
+               void* stream) {
+  drot_cost cost{};
+  cost.kind = DROT_COST_DENSE;
+  cost.data = C;
+  cost.ld = ldc;
+  return drot_solve_cost(c, m, n, dtype, &cost, p, q, prm, X, ldx, mu, nu, mu0, nu0, out, stream);
 }
 
 }  // extern "C"

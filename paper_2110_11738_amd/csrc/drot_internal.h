@@ -33,6 +33,13 @@ enum SweepMode : int {
   kFinalW = 6,  // restores X = W + rho C and evaluates like kFinal
 };
 
+// Where the sweep takes c_ij from.
+enum CostKind : int {
+  kCostDense = 0,   // C stored densely in the problem type
+  kCostBF16 = 1,    // C stored densely as bfloat16 (float32 problems)
+  kCostCoords = 2,  // c_ij = scale * |xs_i - xt_j|^2 from float32 coordinates
+};
+
 // Per-tile scalars: iteration/final: <C,X> and sum [t]_+^2; init: |C|^2 and
 // the count of non-finite entries.
 enum TileSlot : int { kTs0 = 0, kTs1 = 1 };
@@ -66,6 +73,9 @@ struct DevState {
   double sum_phi0, sum_psi0;
   double init_bad;          // count of non-finite entries (C, X_0, p, q, warm start), negative X_0
   double init_neg;          // count of negative marginal entries
+  double cscale;            // coordinates cost: scale (host-given, or 1 / max from maxc)
+  uint32_t maxc_bits;       // coordinates cost: bit pattern of max |xs_i - xt_j|^2 (float)
+  uint32_t pad2;
   // --- iteration ---
   double alpha;             // alpha_k
   double cphi, cpsi;        // scalar parts of phi_k and psi_k: (2 beta - alpha)/n, /m
@@ -93,7 +103,11 @@ struct SweepGeom {
 };
 
 struct SweepArgs {
-  const void* C;
+  int cost_kind;           // CostKind
+  int dim;                 // coordinates cost: point dimension
+  const float* xs;         // coordinates cost: m x dim
+  const float* xt;         // coordinates cost: n x dim
+  const void* C;           // dense cost (problem type) or bfloat16 bit patterns
   void* X;
   const void* p;           // typed like X
   const void* q;
@@ -120,10 +134,12 @@ struct SweepArgs {
 // Tile variant of the sweep: `vec` is 4 (float) / 2 (double) for 16-byte
 // loads or 1 for the scalar fallback; `chunks` the chunks per lane (1/2, or
 // 1/4 on the scalar path); `unroll` the rows kept in flight (4 or 8);
-// `stream` selects nontemporal loads and stores.
+// `stream` selects nontemporal loads and stores.  Ragged widths use 4 rows in
+// flight.
 struct TileCfg {
   int vec, chunks, unroll;
   bool stream;
+  bool ragged;  // 16-byte path with n not a multiple of vec (masked last chunk)
 };
 
 // Launchers (drot_kernels.hip).
@@ -131,5 +147,6 @@ hipError_t launch_sweep(int dtype, int mode, const TileCfg& t, const SweepArgs& 
                         hipStream_t s);
 hipError_t launch_aux(int dtype, int mode, const SweepArgs& a, hipStream_t s);
 hipError_t launch_prep(const SweepArgs& a, hipStream_t s);
+hipError_t launch_maxc(const SweepArgs& a, hipStream_t s);
 
 }  // namespace drot

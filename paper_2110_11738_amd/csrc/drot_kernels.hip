@@ -153,6 +153,24 @@ __device__ __forceinline__ void store_chunk(T* ptr, const T (&in)[VEC]) {
   }
 }
 
+// VEC bfloat16 values (raw 16-bit patterns) widened exactly to float.
+template <int VEC, bool NT>
+__device__ __forceinline__ void load_bf16(const uint16_t* ptr, float (&out)[VEC]) {
+  if constexpr (VEC == 1) {
+    const uint16_t b = NT ? __builtin_nontemporal_load(ptr) : *ptr;
+    out[0] = __builtin_bit_cast(float, (uint32_t)b << 16);
+  } else {
+    static_assert(VEC == 4, "bfloat16 chunks are 4 wide");
+    typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+    const u2* vp = reinterpret_cast<const u2*>(ptr);
+    const u2 v = NT ? __builtin_nontemporal_load(vp) : *vp;
+    out[0] = __builtin_bit_cast(float, v[0] << 16);
+    out[1] = __builtin_bit_cast(float, v[0] & 0xffff0000u);
+    out[2] = __builtin_bit_cast(float, v[1] << 16);
+    out[3] = __builtin_bit_cast(float, v[1] & 0xffff0000u);
+  }
+}
+
 __device__ __forceinline__ bool finite_d(double v) { return __builtin_isfinite(v); }
 
 __device__ __forceinline__ void store_agent(double* p, double v) {
@@ -446,13 +464,14 @@ __global__ __launch_bounds__(kBlock) void aux_kernel(SweepArgs a) {
 // owns CH chunks of VEC consecutive columns and keeps the loads of U rows in
 // flight.  Consecutive workgroups take consecutive strips of the same group.
 // ---------------------------------------------------------------------------
-template <typename T, int MODE, int VEC, int CH, int U, bool NT>
+template <typename T, int MODE, int VEC, int CH, int U, bool NT, int CM, int D, bool RAGGED>
 __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a) {
   using P = typename PartialOf<T, MODE>::type;
   using A = typename std::conditional<is_final(MODE), double, T>::type;
   constexpr int CPL = VEC * CH;
   constexpr int W = kWave * CPL;
-  constexpr bool kReadC = MODE != kIterB;
+  constexpr bool kReadC = MODE != kIterB && CM != kCostCoords;
+  static_assert(CM == kCostDense || std::is_same<T, float>::value, "cost kind needs float32");
   constexpr bool kReadX = MODE != kInitPQ;
   constexpr bool kWriteX = MODE != kInitX && MODE != kFinal;
 
@@ -468,15 +487,23 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a) {
   const int rpw = (a.g.rows + kWaves - 1) / kWaves;
 
   const T* __restrict__ C = static_cast<const T*>(a.C);
+  const uint16_t* __restrict__ Cb = static_cast<const uint16_t*>(a.C);
   T* __restrict__ X = static_cast<T*>(a.X);
 
-  // Column layout of this lane: chunk c covers [jc[c], jc[c] + VEC).
+  // Column layout of this lane: chunk c covers [jc[c], jc[c] + VEC), of which
+  // nv[c] columns lie inside the matrix.  A chunk that straddles column n is
+  // loaded whole (the leading dimensions are multiples of VEC, so the load
+  // stays inside the row) but only its valid elements count and are stored.
   int64_t jc[CH];
+  int nv[CH];
   bool ok[CH];
 #pragma unroll
   for (int c = 0; c < CH; ++c) {
     jc[c] = col0 + (int64_t)c * kWave * VEC + (int64_t)lane * VEC;
-    ok[c] = jc[c] < n;  // the vector path is only used when n % VEC == 0
+    const int64_t left = n - jc[c];
+    if constexpr (RAGGED) nv[c] = left <= 0 ? 0 : (left >= VEC ? VEC : (int)left);
+    else nv[c] = left > 0 ? VEC : 0;  // n is a multiple of VEC
+    ok[c] = nv[c] > 0;
   }
 
   // Column shift of this lane's columns (or q_j for X_0 = p q^T).
@@ -486,7 +513,7 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a) {
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
       A v = 0;
-      if (ok[c]) {
+      if (e < nv[c]) {
         const int64_t j = jc[c] + e;
         if (is_iter(MODE)) v = static_cast<const T*>(a.psiT)[j];
         if (is_final(MODE)) v = a.psi64[j];
@@ -494,6 +521,20 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a) {
       }
       colv[c][e] = v;
     }
+
+  // Coordinates of this lane's target points (coordinates cost only).
+  constexpr int DD = CM == kCostCoords ? D : 1;
+  float xtl[CH][VEC][DD];
+  float cscale = 0.f;
+  if constexpr (CM == kCostCoords) {
+    cscale = (float)st->cscale;
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e)
+#pragma unroll
+        for (int d = 0; d < D; ++d) xtl[c][e][d] = e < nv[c] ? a.xt[(jc[c] + e) * D + d] : 0.f;
+  }
 
   A shift = 0, rho = 0;
   T rhoT = 0;
@@ -519,19 +560,40 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a) {
   const int64_t rw1 = rw0 + rpw < rowE ? rw0 + rpw : rowE;
   for (int64_t i0 = rw0; i0 < rw1; i0 += U) {
     T xv[U][CH][VEC], cv[U][CH][VEC];
+    float xsr[U][DD];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t i = i0 + u;
       if (i < rw1) {
+        if constexpr (CM == kCostCoords)
+#pragma unroll
+          for (int d = 0; d < D; ++d) xsr[u][d] = a.xs[i * D + d];
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
           if (ok[c]) {
-            if (kReadC) load_chunk<T, VEC, NT>(C + i * a.g.ldc + jc[c], cv[u][c]);
+            if constexpr (kReadC && CM == kCostDense)
+              load_chunk<T, VEC, NT>(C + i * a.g.ldc + jc[c], cv[u][c]);
+            if constexpr (kReadC && CM == kCostBF16)
+              load_bf16<VEC, NT>(Cb + i * a.g.ldc + jc[c], cv[u][c]);
             if (kReadX) load_chunk<T, VEC, NT>(X + i * a.g.ldx + jc[c], xv[u][c]);
           }
         }
       }
     }
+    // c_ij as the storage type sees it.
+    auto cost = [&](int u, int c, int e) -> T {
+      if constexpr (CM == kCostCoords) {
+        float s = 0.f;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          const float df = xsr[u][d] - xtl[c][e][d];
+          s += df * df;
+        }
+        return (T)(s * cscale);
+      } else {
+        return cv[u][c][e];
+      }
+    };
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t i = i0 + u;
@@ -547,14 +609,17 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a) {
             T outv[VEC];
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
-              A x;
-              if constexpr (MODE == kIterB) {
+              A x = 0;
+              if (RAGGED && e >= nv[c]) {
+                // beyond column n (padding): contributes nothing, never stored
+                outv[e] = (T)0;
+              } else if constexpr (MODE == kIterB) {
                 // X_{k+2} = [W + phi_i + psi_j]_+ with W = X_{k+1} - rho C.
                 const A y = (A)xv[u][c][e] + (rowv + colv[c][e]);
                 x = y > (A)0 ? y : (A)0;
                 outv[e] = (T)x;
               } else if constexpr (is_iter(MODE) || is_final(MODE)) {
-                const A cij = (A)cv[u][c][e];
+                const A cij = (A)cost(u, c, e);
                 const A pc = is_final(MODE) ? rho * cij : mul_rounded<A>(rho, cij);
                 const A t = rowv + colv[c][e] - pc;
                 const A tp = t > (A)0 ? t : (A)0;
@@ -575,7 +640,7 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a) {
                 }
                 s0 += (P)(cij * x);
               } else {
-                const A cij = (A)cv[u][c][e];
+                const A cij = (A)cost(u, c, e);
                 if (MODE == kInitPQ) x = rowv * colv[c][e];
                 else x = (A)xv[u][c][e];
                 s0 += (P)((double)cij * (double)cij);
@@ -587,7 +652,13 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a) {
               rsum += (P)x;
               colacc[c][e] += (P)x;
             }
-            if (kWriteX) store_chunk<T, VEC, NT>(X + i * a.g.ldx + jc[c], outv);
+            if (kWriteX) {
+              if (!RAGGED || nv[c] == VEC) {
+                store_chunk<T, VEC, NT>(X + i * a.g.ldx + jc[c], outv);
+              } else {
+                for (int e = 0; e < nv[c]; ++e) X[i * a.g.ldx + jc[c] + e] = outv[e];
+              }
+            }
           }
         }
         const P tot = wave_sum(rsum);
@@ -650,6 +721,10 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(SweepArgs a) {
     DevState* st = a.st;
     st->sum_phi0 = st->rho * acc[0];
     st->sum_psi0 = st->rho * acc[1];
+    if (a.cost_kind == kCostCoords && !(st->cscale > 0.0)) {
+      const float mx = __uint_as_float(st->maxc_bits);
+      st->cscale = mx > 0.f ? 1.0 / (double)mx : 1.0;
+    }
     st->t_start = wall_clock64();
     st->t_stop = st->t_start;
     st->t_last = st->t_start;
@@ -657,19 +732,36 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(SweepArgs a) {
   }
 }
 
-template <typename T, int MODE, int VEC, int CH, int U, bool NT>
+template <typename T, int MODE, int VEC, int CH, int U, bool NT, int CM = kCostDense, int D = 1,
+          bool RAGGED = false>
 hipError_t sweep_go(const SweepArgs& a, hipStream_t s) {
   const int64_t tiles = (int64_t)a.g.n_ct * a.g.n_rg;
-  hipLaunchKernelGGL((sweep_kernel<T, MODE, VEC, CH, U, NT>), dim3((unsigned)tiles), dim3(kBlock), 0,
-                     s, a);
+  hipLaunchKernelGGL((sweep_kernel<T, MODE, VEC, CH, U, NT, CM, D, RAGGED>), dim3((unsigned)tiles),
+                     dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
-// The iteration instantiates every tile variant; initialisation and the final
-// evaluation run once per solve and use the plain 4-row, cached variant.
-template <typename T, int MODE>
-hipError_t sweep_mode(const TileCfg& t, const SweepArgs& a, hipStream_t s) {
+// 16-byte path with n not a multiple of the vector width (masked last chunk):
+// 1 or 2 chunks, 4 rows in flight, cached or streaming.
+template <typename T, int MODE, int CM, int D>
+hipError_t sweep_ragged(const TileCfg& t, const SweepArgs& a, hipStream_t s) {
   constexpr int V = 16 / sizeof(T);
+  if (t.vec != V || t.unroll != 4) return hipErrorInvalidValue;
+  switch ((t.chunks == 2 ? 1 : 0) | (t.stream ? 2 : 0)) {
+    case 0: return sweep_go<T, MODE, V, 1, 4, false, CM, D, true>(a, s);
+    case 1: return sweep_go<T, MODE, V, 2, 4, false, CM, D, true>(a, s);
+    case 2: return sweep_go<T, MODE, V, 1, 4, true, CM, D, true>(a, s);
+    case 3: return sweep_go<T, MODE, V, 2, 4, true, CM, D, true>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// The iteration instantiates every tile variant; initialisation and the final
+// evaluation run once per solve and use the plain 4-row variant.
+template <typename T, int MODE>
+hipError_t sweep_dense(const TileCfg& t, const SweepArgs& a, hipStream_t s) {
+  constexpr int V = 16 / sizeof(T);
+  if (t.ragged) return sweep_ragged<T, MODE, kCostDense, 1>(t, a, s);
   if (t.vec == 1) {
     if (t.chunks == 1) return sweep_go<T, MODE, 1, 1, 4, false>(a, s);
     if (t.chunks == 4) return sweep_go<T, MODE, 1, 4, 4, false>(a, s);
@@ -696,6 +788,43 @@ hipError_t sweep_mode(const TileCfg& t, const SweepArgs& a, hipStream_t s) {
   }
 }
 
+// Non-dense cost sources (float32 only): 1 or 2 chunks, 4 rows in flight,
+// cached or streaming; the scalar path uses 4 chunks, cached.
+template <int MODE, int CM, int D>
+hipError_t sweep_cost(const TileCfg& t, const SweepArgs& a, hipStream_t s) {
+  if (t.ragged) return sweep_ragged<float, MODE, CM, D>(t, a, s);
+  if (t.vec == 1) {
+    if (t.chunks == 4) return sweep_go<float, MODE, 1, 4, 4, false, CM, D>(a, s);
+    return hipErrorInvalidValue;
+  }
+  if (t.vec != 4 || t.unroll != 4) return hipErrorInvalidValue;
+  const int key = (t.chunks == 2 ? 1 : 0) | (t.stream ? 2 : 0);
+  switch (key) {
+    case 0: return sweep_go<float, MODE, 4, 1, 4, false, CM, D>(a, s);
+    case 1: return sweep_go<float, MODE, 4, 2, 4, false, CM, D>(a, s);
+    case 2: return sweep_go<float, MODE, 4, 1, 4, true, CM, D>(a, s);
+    case 3: return sweep_go<float, MODE, 4, 2, 4, true, CM, D>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int MODE>
+hipError_t sweep_mode(const TileCfg& t, const SweepArgs& a, hipStream_t s) {
+  if (a.cost_kind == kCostDense) return sweep_dense<T, MODE>(t, a, s);
+  if constexpr (std::is_same<T, float>::value && !(MODE == kIterA || MODE == kIterB ||
+                                                   MODE == kFinalW)) {
+    if (a.cost_kind == kCostBF16) return sweep_cost<MODE, kCostBF16, 1>(t, a, s);
+    if (a.cost_kind == kCostCoords) {
+      switch (a.dim) {
+        case 1: return sweep_cost<MODE, kCostCoords, 1>(t, a, s);
+        case 2: return sweep_cost<MODE, kCostCoords, 2>(t, a, s);
+        case 3: return sweep_cost<MODE, kCostCoords, 3>(t, a, s);
+      }
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
 template <typename T>
 hipError_t sweep_type(int mode, const TileCfg& t, const SweepArgs& a, hipStream_t s) {
   switch (mode) {
@@ -708,6 +837,37 @@ hipError_t sweep_type(int mode, const TileCfg& t, const SweepArgs& a, hipStream_
     case kFinalW: return sweep_mode<T, kFinalW>(t, a, s);
   }
   return hipErrorInvalidValue;
+}
+
+// max_ij |xs_i - xt_j|^2 for the coordinates cost (scale = 1 / max when the
+// caller gives none).  A block covers 256 targets and up to 256 sources; the
+// maximum of nonnegative floats is taken on their bit patterns, which order
+// the same way, so the result does not depend on the order of the atomics.
+template <int D>
+__global__ __launch_bounds__(kBlock) void maxc_kernel(SweepArgs a) {
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.y * kBlock;
+  const int64_t i1 = i0 + kBlock < a.g.m ? i0 + kBlock : a.g.m;
+  float mx = 0.f;
+  if (j < a.g.n) {
+    float yt[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) yt[d] = a.xt[j * D + d];
+    for (int64_t i = i0; i < i1; ++i) {
+      float s = 0.f;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const float df = a.xs[i * D + d] - yt[d];
+        s += df * df;
+      }
+      mx = s > mx ? s : mx;
+    }
+  }
+  for (int off = kWave / 2; off > 0; off /= 2) {
+    const float o = __shfl_xor(mx, off);
+    mx = o > mx ? o : mx;
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(&a.st->maxc_bits, __float_as_uint(mx));
 }
 
 template <typename T>
@@ -735,6 +895,17 @@ hipError_t launch_aux(int dtype, int mode, const SweepArgs& a, hipStream_t s) {
 hipError_t launch_sweep(int dtype, int mode, const TileCfg& t, const SweepArgs& a,
                         hipStream_t s) {
   return dtype == 0 ? sweep_type<float>(mode, t, a, s) : sweep_type<double>(mode, t, a, s);
+}
+
+hipError_t launch_maxc(const SweepArgs& a, hipStream_t s) {
+  const dim3 grid((unsigned)((a.g.n + kBlock - 1) / kBlock), (unsigned)((a.g.m + kBlock - 1) / kBlock));
+  switch (a.dim) {
+    case 1: hipLaunchKernelGGL(maxc_kernel<1>, grid, dim3(kBlock), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(maxc_kernel<2>, grid, dim3(kBlock), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(maxc_kernel<3>, grid, dim3(kBlock), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_prep(const SweepArgs& a, hipStream_t s) {

@@ -24,11 +24,12 @@ TOL_RELATIVE, TOL_ABSOLUTE = 0, 1
 X0_PQ, X0_GIVEN = 0, 1
 FLAG_NO_GRAPH, FLAG_TIME_SWEEP, FLAG_SKIP_C = 0x1, 0x2, 0x4
 CACHE_AUTO, CACHE_CACHED, CACHE_STREAM = 0, 1, 2
+COST_DENSE, COST_BF16, COST_COORDS = 0, 1, 2
 TRACE_FIELDS = ("pobj", "dobj", "r_primal", "r_dual_lag", "gap", "test", "seconds", "k")
 
 EXPORTED = ("drot_version", "drot_strerror", "drot_last_error", "drot_ctx_create",
             "drot_ctx_destroy", "drot_solve", "drot_bind", "drot_iterate", "drot_poll",
-            "drot_finish", "drot_get_trace")
+            "drot_finish", "drot_get_trace", "drot_bind_cost", "drot_solve_cost")
 
 
 class Params(ctypes.Structure):
@@ -49,10 +50,16 @@ class Result(ctypes.Structure):
                 ("eps_primal", ctypes.c_double), ("eps_dual", ctypes.c_double),
                 ("eps_gap", ctypes.c_double), ("seconds_to_tol", ctypes.c_double),
                 ("seconds_total", ctypes.c_double), ("sweep_ms_total", ctypes.c_double),
-                ("sweep_timed", ctypes.c_int64)]
+                ("sweep_timed", ctypes.c_int64), ("cost_scale", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class Cost(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("dim", ctypes.c_int32), ("data", ctypes.c_void_p),
+                ("ld", ctypes.c_int64), ("xs", ctypes.c_void_p), ("xt", ctypes.c_void_p),
+                ("scale", ctypes.c_double)]
 
 
 class DrotError(RuntimeError):
@@ -87,6 +94,10 @@ def lib():
     L.drot_poll.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int32), vp]
     L.drot_finish.argtypes = [vp, vp, vp, ctypes.POINTER(Result), vp]
     L.drot_get_trace.argtypes = [vp, i64, i64, ctypes.POINTER(ctypes.c_double)]
+    cost_common = [vp, i64, i64, i32, ctypes.POINTER(Cost), vp, vp, ctypes.POINTER(Params), vp,
+                   i64]
+    L.drot_bind_cost.argtypes = cost_common + [vp, vp, vp]
+    L.drot_solve_cost.argtypes = cost_common + [vp, vp, vp, vp, ctypes.POINTER(Result), vp]
     for name in EXPORTED:
         getattr(L, name).restype = getattr(L, name).restype or i32
     _lib = L
@@ -189,6 +200,14 @@ class Context:
         _check(rc, allow=(OK,))
         return out
 
+    def bind_cost(self, m, n, cost: "Cost", p, q, X, params: Params, mu0=None, nu0=None,
+                  stream=None, keep=()):
+        self._keep = (p, q, X, mu0, nu0) + tuple(keep)
+        rc = lib().drot_bind_cost(self.handle, m, n, _dtype_code(X), ctypes.byref(cost), _ptr(p),
+                                  _ptr(q), ctypes.byref(params), _ptr(X), _ld(X), _ptr(mu0),
+                                  _ptr(nu0), _stream(stream))
+        return _check(rc, allow=(OK,))
+
     # -- one-call solve ----------------------------------------------------
     def solve(self, C, p, q, params: Params, X=None, mu=None, nu=None, mu0=None, nu0=None,
               stream=None):
@@ -204,6 +223,19 @@ class Context:
         return X, r.as_dict()
 
 
+def make_cost(kind: int, C=None, xs=None, xt=None, scale: float = 0.0) -> Cost:
+    """Cost descriptor: COST_DENSE / COST_BF16 take a 2-D tensor C (float32 or
+    float64 / bfloat16), COST_COORDS the float32 point arrays xs (m x d) and
+    xt (n x d) and an optional scale (0 = 1/max computed on the device)."""
+    if kind == COST_COORDS:
+        if xs is None or xt is None or xs.dim() != 2 or xt.dim() != 2 or xs.shape[1] != xt.shape[1]:
+            raise ValueError("coordinates need xs (m x d) and xt (n x d)")
+        if not (xs.is_contiguous() and xt.is_contiguous()):
+            raise ValueError("coordinates must be contiguous")
+        return Cost(COST_COORDS, xs.shape[1], None, 0, xs.data_ptr(), xt.data_ptr(), float(scale))
+    return Cost(int(kind), 0, C.data_ptr(), _ld(C), None, None, 0.0)
+
+
 _default_ctx: dict = {}
 
 
@@ -211,6 +243,33 @@ def default_context(device: int = 0) -> Context:
     if device not in _default_ctx:
         _default_ctx[device] = Context(device)
     return _default_ctx[device]
+
+
+def solve_cost(m: int, n: int, p, q, rho: float, kind: int, C=None, xs=None, xt=None,
+               scale: float = 0.0, tol: float = 1e-4, max_iter: int = 100000,
+               tol_mode: int = TOL_RELATIVE, X0=None, mu0=None, nu0=None, check_every: int = 0,
+               flags: int = 0, tile_rows: int = 0, tile_chunks: int = 0, tile_unroll: int = 0,
+               cache_mode: int = CACHE_AUTO, tile_groups: int = 0, ctx: Context | None = None,
+               stream=None):
+    """solve() with a cost descriptor (see make_cost); X and the marginals are
+    float32 for the bfloat16 and coordinate costs."""
+    import torch
+    dev = p.device
+    ctx = ctx or default_context(dev.index or 0)
+    dt = p.dtype
+    X = torch.empty((m, n), dtype=dt, device=dev) if X0 is None else X0
+    mu = torch.empty(m, dtype=torch.float64, device=dev)
+    nu = torch.empty(n, dtype=torch.float64, device=dev)
+    prm = make_params(rho, tol, max_iter, tol_mode, X0_PQ if X0 is None else X0_GIVEN,
+                      check_every, flags, tile_rows, tile_chunks, tile_unroll, cache_mode,
+                      tile_groups)
+    cost = make_cost(kind, C, xs, xt, scale)
+    r = Result()
+    rc = lib().drot_solve_cost(ctx.handle, m, n, _dtype_code(X), ctypes.byref(cost), _ptr(p),
+                               _ptr(q), ctypes.byref(prm), _ptr(X), _ld(X), _ptr(mu), _ptr(nu),
+                               _ptr(mu0), _ptr(nu0), ctypes.byref(r), _stream(stream))
+    _check(rc)
+    return X, r.as_dict(), mu, nu
 
 
 @dataclass

@@ -335,3 +335,99 @@ def test_row_groups_agree_with_oracle(ctx, rows, groups):
     assert _rel_max(Xg, R.X) <= TOL["float32"][0]
     assert _rel_max(mu, R.mu) <= TOL["float32"][1]
     assert abs(res["objective"] - R.info["pobj"]) <= TOL["float32"][2] * R.info["pobj"]
+
+
+# ---------------------------------------------------------------------------
+# Reduced-byte cost sources: bfloat16 C and C regenerated from coordinates
+# ---------------------------------------------------------------------------
+def _coords_problem(seed, m, n, d):
+    """float32 coordinates, the FP64 cost the oracle uses for them, and
+    float32 marginals."""
+    from gen import dirichlet1
+    rng = np.random.default_rng([15, seed, m, n, d])
+    xs = rng.uniform(0, 1, (m, d)).astype(np.float32)
+    xt = rng.uniform(0, 1, (n, d)).astype(np.float32)
+    xs64, xt64 = xs.astype(np.float64), xt.astype(np.float64)
+    D = ((xs64[:, None, :] - xt64[None, :, :]) ** 2).sum(-1)
+    scale = 1.0 / D.max()
+    p = dirichlet1(rng, m).astype(np.float32).astype(np.float64)
+    q = dirichlet1(rng, n).astype(np.float32).astype(np.float64)
+    return xs, xt, D, scale, p, q
+
+
+@pytest.mark.parametrize("m,n,d,given", [(300, 520, 3, True), (257, 130, 2, False),
+                                         (64, 203, 1, True), (129, 1030, 3, False)])
+def test_coordinate_cost_trajectory(ctx, m, n, d, given):
+    """c_ij regenerated in float32 from coordinates: the trajectory matches the
+    oracle run on the FP64 cost of the same coordinates (n = 203 and 1030 take
+    the scalar and 2-chunk paths); the device-computed scale is 1/max."""
+    torch = _torch()
+    from paper_2110_11738_amd import drot
+    xs, xt, D, scale, p, q = _coords_problem(0, m, n, d)
+    C64 = D * scale
+    rho = 1.0 / np.log(m) / (m + n)
+    dev = "cuda"
+    K = 20
+    X, res, mu, nu = drot.solve_cost(m, n, torch.tensor(p, dtype=torch.float32, device=dev),
+                                     torch.tensor(q, dtype=torch.float32, device=dev), rho,
+                                     drot.COST_COORDS, xs=torch.tensor(xs, device=dev),
+                                     xt=torch.tensor(xt, device=dev),
+                                     scale=scale if given else 0.0, tol=0.0, max_iter=K, ctx=ctx)
+    torch.cuda.synchronize()
+    assert abs(res["cost_scale"] - scale) <= 1e-6 * scale
+    R = ref.solve(C64, p, q, rho, 0.0, max_iter=K)
+    Xg = X.double().cpu().numpy()
+    print(f"[coords] {m}x{n} d={d}: X {_rel_max(Xg, R.X):.2e} mu {_rel_max(mu.cpu().numpy(), R.mu):.2e}")
+    assert _rel_max(Xg, R.X) <= TOL["float32"][0]
+    assert _rel_max(mu.cpu().numpy(), R.mu) <= TOL["float32"][1]
+    assert abs(res["objective"] - R.info["pobj"]) <= 1e-5 * R.info["pobj"]
+
+
+def test_bf16_cost_trajectory_and_error_statement(ctx):
+    """bfloat16 C: parity with the oracle on the bfloat16-rounded problem, and
+    the error of the answer against the float32 problem stays inside the
+    a-priori bound 2u/(1-u), u = 2^-8 (every c_ij moves by at most u c_ij)."""
+    torch = _torch()
+    from paper_2110_11738_amd import drot
+    inst = round_to(config_mixture_2d(16, 256, 384), np.float32)
+    Cb = torch.tensor(inst.C, dtype=torch.float32).to(torch.bfloat16)
+    C16 = Cb.float().double().numpy()
+    p = torch.tensor(inst.p, dtype=torch.float32, device="cuda")
+    q = torch.tensor(inst.q, dtype=torch.float32, device="cuda")
+    Cb = Cb.cuda()
+    K = 25
+    X, res, mu, nu = drot.solve_cost(256, 384, p, q, inst.rho, drot.COST_BF16, C=Cb, tol=0.0,
+                                     max_iter=K, ctx=ctx)
+    R = ref.solve(C16, inst.p, inst.q, inst.rho, 0.0, max_iter=K)
+    assert _rel_max(X.double().cpu().numpy(), R.X) <= TOL["float32"][0]
+    assert _rel_max(mu.cpu().numpy(), R.mu) <= TOL["float32"][1]
+    # full solves: bfloat16 cost vs float32 cost
+    Xb, rb, mub, nub = drot.solve_cost(256, 384, p, q, inst.rho, drot.COST_BF16, C=Cb, tol=1e-5,
+                                       max_iter=2_000_000, ctx=ctx)
+    Xf, rf, muf, nuf = _run(ctx, inst, "float32", 2_000_000, tol=1e-5)
+    u = 2.0 ** -8
+    err = abs(rb["objective"] - rf["objective"]) / rf["objective"]
+    print(f"[bf16] objective {rb['objective']:.8e} vs float32 C {rf['objective']:.8e}: rel {err:.2e}")
+    assert rb["status"] == 0 and err <= 2 * u / (1 - u)
+
+
+@pytest.mark.parametrize("dtype", ["float32", "float64"])
+def test_ragged_width_on_the_vector_path(ctx, dtype):
+    """n = 203 with leading dimension 204 (a multiple of the vector width):
+    the 16-byte path handles the straddling chunk and leaves padding alone."""
+    torch = _torch()
+    from paper_2110_11738_amd import drot
+    inst = _rounded(config_mixture_2d(17, 150, 203), dtype)
+    tdt = torch.float32 if dtype == "float32" else torch.float64
+    Cbig = torch.full((150, 204), 5.0, dtype=tdt, device="cuda")
+    Cbig[:, :203] = torch.tensor(inst.C, dtype=tdt, device="cuda")
+    Xbig = torch.full((150, 204), -2.0, dtype=tdt, device="cuda")
+    p = torch.tensor(inst.p, dtype=tdt, device="cuda")
+    q = torch.tensor(inst.q, dtype=tdt, device="cuda")
+    prm = drot.make_params(inst.rho, 0.0, 15)
+    X, res = ctx.solve(Cbig[:, :203], p, q, prm, X=Xbig[:, :203])
+    torch.cuda.synchronize()
+    R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=15)
+    assert _rel_max(X.double().cpu().numpy(), R.X) <= TOL[dtype][0]
+    assert torch.all(Xbig[:, 203] == -2.0)
+    assert abs(res["objective"] - R.info["pobj"]) <= TOL[dtype][2] * R.info["pobj"]

@@ -26,6 +26,7 @@ def lib():
 def test_header_declares_the_documented_entry_points():
     names = _declared()
     for must in ("drot_solve", "drot_bind", "drot_iterate", "drot_poll", "drot_finish",
+                 "drot_solve_cost", "drot_bind_cost",
                  "drot_ctx_create", "drot_ctx_destroy", "drot_get_trace", "drot_last_error",
                  "drot_strerror", "drot_version"):
         assert must in names
@@ -44,9 +45,10 @@ def test_binding_covers_every_export():
 def test_struct_layouts_match_header(lib):
     from paper_2110_11738_amd import drot
     # drot_params: 2 doubles, 1 int64, 10 int32 -> 64 bytes;
-    # drot_result: int64, 2 int32, 11 doubles, int64 -> 112 bytes
+    # drot_result: int64, 2 int32, 11 doubles, int64, double -> 120 bytes
     assert ctypes.sizeof(drot.Params) == 64
-    assert ctypes.sizeof(drot.Result) == 112
+    assert ctypes.sizeof(drot.Result) == 120
+    assert ctypes.sizeof(drot.Cost) == 48
 
 
 def test_version_and_strerror(lib):
@@ -111,3 +113,24 @@ def test_product_path_does_not_import_the_oracle():
             "bad = [m for m in sys.modules if m == 'oracle' or m.startswith('oracle.')]; "
             "print(bad); assert not bad" % ROOT)
     subprocess.run([sys.executable, "-c", code], check=True, cwd=ROOT)
+
+
+def test_cost_descriptor_validation_without_device(lib):
+    from paper_2110_11738_amd import drot
+    prm = drot.make_params(0.1, 1e-4, 100)
+    res = drot.Result()
+
+    def go(cost, dtype=0):
+        return lib.drot_solve_cost(None, 4, 8, dtype, ctypes.byref(cost) if cost else None,
+                                   4096 * 1000, 4096 * 2000, ctypes.byref(prm), 4096 * 5000, 8,
+                                   None, None, None, None, ctypes.byref(res), None)
+    assert go(None) == drot.EINVAL
+    assert go(drot.Cost(7, 0, 4096, 8, None, None, 0.0)) == drot.EINVAL
+    assert go(drot.Cost(drot.COST_COORDS, 5, None, 0, 4096, 8192, 0.0)) == drot.EINVAL
+    assert go(drot.Cost(drot.COST_COORDS, 2, None, 0, None, 8192, 0.0)) == drot.EINVAL
+    assert go(drot.Cost(drot.COST_COORDS, 2, None, 0, 4096, 8192, -1.0)) == drot.EINVAL
+    assert go(drot.Cost(drot.COST_BF16, 0, 4096, 8, None, None, 0.0), dtype=1) == drot.EUNSUPPORTED
+    assert go(drot.Cost(drot.COST_BF16, 0, 4096, 4, None, None, 0.0)) == drot.EINVAL  # ld < n
+    # a valid descriptor reaches the context check
+    assert go(drot.Cost(drot.COST_COORDS, 3, None, 0, 4096, 8192, 0.0)) == drot.EINVAL
+    assert "ctx" in drot.last_error()
