@@ -56,12 +56,19 @@ def upload(inst):
 
 def timed_iterations(ctx, C, p, q, rho, steps, warmup, args, timed_events=True):
     """Bind, warm up, then time exactly `steps` iterations.  Returns
-    (seconds, sweep_ms_avg or None, sweep_count)."""
+    (seconds, sweep_ms_avg or None, sweep_count, result)."""
+    from paper_2110_11738_amd import drot
+    return timed_iterations_flags(ctx, C, p, q, rho, steps, warmup, args,
+                                  drot.FLAG_TIME_SWEEP if timed_events else 0)
+
+
+def timed_iterations_flags(ctx, C, p, q, rho, steps, warmup, args, flags):
     import torch
     from paper_2110_11738_amd import drot
     m, n = C.shape
     X = torch.empty((m, n), dtype=C.dtype, device=C.device)
-    flags = drot.FLAG_TIME_SWEEP if timed_events else 0
+    if flags & drot.FLAG_SKIP_C:
+        flags |= drot.FLAG_TIME_SWEEP
     prm = drot.make_params(rho, 0.0, warmup + steps + 1, check_every=args.check_every,
                            flags=flags, tile_rows=args.tile_rows, tile_chunks=args.tile_chunks,
                            tile_unroll=args.tile_unroll, cache_mode=args.cache_mode,
@@ -82,6 +89,107 @@ def timed_iterations(ctx, C, p, q, rho, steps, warmup, args, timed_events=True):
     cnt = res["sweep_timed"] - n0
     avg = (res["sweep_ms_total"] - ms0) / cnt if cnt > 0 else None
     return t1 - t0, avg, cnt, res
+
+
+def timed_cost_iterations(ctx, m, n, cost, p, q, rho, steps, warmup, keep):
+    """Like timed_iterations for a cost descriptor (bfloat16 / coordinates)."""
+    import torch
+    from paper_2110_11738_amd import drot
+    X = torch.empty((m, n), dtype=torch.float32, device="cuda")
+    prm = drot.make_params(rho, 0.0, warmup + steps + 1, check_every=64,
+                           flags=drot.FLAG_TIME_SWEEP)
+    ctx.bind_cost(m, n, cost, p, q, X, prm, keep=keep)
+    ctx.iterate(warmup)
+    torch.cuda.synchronize()
+    before = ctx.finish()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.iterate(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    res = ctx.finish()
+    cnt = res["sweep_timed"] - before["sweep_timed"]
+    return t1 - t0, (res["sweep_ms_total"] - before["sweep_ms_total"]) / cnt
+
+
+def precision_section(ctx, steps=200, warmup=20):
+    """10000 x 15000, points uniform in the unit cube of R^3: the same
+    iteration with C dense float32 (12 B/entry), bfloat16 (10 B/entry) and
+    regenerated from float32 coordinates (8 B/entry)."""
+    import numpy as np
+    import torch
+    from gen import config_cube_3d
+    from paper_2110_11738_amd import drot
+    t0 = time.time()
+    inst = config_cube_3d(0)
+    m, n = inst.m, inst.n
+    log(f"generated {inst.name} in {time.time() - t0:.1f}s")
+    C32 = torch.from_numpy(inst.C.astype(np.float32)).cuda()
+    Cb = C32.to(torch.bfloat16)
+    xs = torch.from_numpy(inst.xs.astype(np.float32)).cuda()
+    xt = torch.from_numpy(inst.xt.astype(np.float32)).cuda()
+    p = torch.from_numpy(inst.p.astype(np.float32)).cuda()
+    q = torch.from_numpy(inst.q.astype(np.float32)).cuda()
+    rho = inst.rho
+    scale = float(inst.cscale)
+    del inst
+    out = {"m": m, "n": n, "workload": "cube3d 10000x15000 float32 X"}
+    for name, kind, keep, bpe in (("dense_f32", drot.COST_DENSE, (C32,), 12),
+                                  ("bf16", drot.COST_BF16, (Cb,), 10),
+                                  ("coords", drot.COST_COORDS, (xs, xt), 8)):
+        cost = drot.make_cost(kind, C=C32 if kind == drot.COST_DENSE else Cb, xs=xs, xt=xt,
+                              scale=scale)
+        secs, sw = timed_cost_iterations(ctx, m, n, cost, p, q, rho, steps, warmup, keep)
+        ach = bpe * m * n / (sw * 1e-3) / 1e9
+        out[name] = {"iter_per_s": steps / secs, "sweep_us": sw * 1e3, "bytes_per_entry": bpe,
+                     "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS}
+        log(f"precision {name}: {steps / secs:.1f} it/s, sweep {sw * 1e3:.1f} us, "
+            f"{ach:.0f} GB/s ({bpe} B/entry)")
+    del C32, Cb, xs, xt
+    torch.cuda.empty_cache()
+    return out
+
+
+def batch_section(ctx, count=512, iters=100):
+    """512 ragged problems (m, n uniform in [64, 2048]) advanced together for
+    a fixed number of iterations, against the same problems solved one by one."""
+    import numpy as np
+    import torch
+    from gen import config_batch
+    from paper_2110_11738_amd import drot
+    t0 = time.time()
+    insts = config_batch(count)
+    log(f"generated {count} batch problems in {time.time() - t0:.1f}s")
+    probs = []
+    entries = 0
+    for I in insts:
+        probs.append({"C": drot.padded(torch.from_numpy(I.C.astype(np.float32)).cuda()),
+                      "p": torch.from_numpy(I.p.astype(np.float32)).cuda(),
+                      "q": torch.from_numpy(I.q.astype(np.float32)).cuda(),
+                      "rho": I.rho, "tol": 0.0})
+        entries += I.m * I.n
+    del insts
+    drot.solve_batched(probs[:8], max_iter=5, ctx=ctx)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, outs = drot.solve_batched(probs, max_iter=iters, check_every=50, ctx=ctx)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    assert all(o[1]["iters"] == iters for o in outs)
+    del outs
+    t0 = time.perf_counter()
+    for pr in probs:
+        drot.solve(pr["C"], pr["p"], pr["q"], pr["rho"], tol=0.0, max_iter=iters, check_every=50,
+                   ctx=ctx)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    gbs = 12.0 * entries * iters / t_batch / 1e9
+    log(f"batch of {count}: {t_batch:.3f}s batched vs {t_seq:.3f}s one by one "
+        f"({t_seq / t_batch:.1f}x), {gbs:.0f} GB/s")
+    return {"problems": count, "iterations": iters, "entries": entries,
+            "seconds_batched": t_batch, "seconds_one_by_one": t_seq,
+            "speedup": t_seq / t_batch, "achieved_GBs": gbs,
+            "workload": "config_batch: m, n ~ U[64, 2048], 2-D blob clouds, Dirichlet(1), float32"}
 
 
 def cpu_baseline(inst, budget_s=20.0):
@@ -133,6 +241,9 @@ def main():
     ap.add_argument("--tile-unroll", type=int, default=0)
     ap.add_argument("--cache-mode", type=int, default=0, help="0 auto, 1 cached, 2 streaming")
     ap.add_argument("--tile-groups", type=int, default=0)
+    ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-skipc", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration for profiles)")
     ap.add_argument("--check-every", type=int, default=64)
@@ -187,6 +298,20 @@ def main():
         "roofline": roof,
     }
 
+    # ---- the paper's skip-C schedule on the same workload ---------------------
+    if not args.no_skipc:
+        class _A:
+            pass
+        sk = _A()
+        for k, v in vars(args).items():
+            setattr(sk, k, v)
+        secs_s, sweep_s, _, _ = timed_iterations_flags(ctx, C, p, q, inst.rho, args.steps,
+                                                       args.warmup, sk, drot.FLAG_SKIP_C)
+        out["skip_c"] = {"iter_per_s": args.steps / secs_s, "avg_sweep_us": sweep_s * 1e3,
+                         "bytes_per_entry_avg": 10,
+                         "achieved_GBs": 10 * m * n / (sweep_s * 1e-3) / 1e9}
+        log(f"skip-C: {args.steps / secs_s:.1f} it/s, average sweep {sweep_s * 1e3:.2f} us")
+
     # ---- time to the 1e-4 relative stopping test -----------------------------
     if not args.no_tol:
         X = torch.empty((m, n), dtype=torch.float32, device="cuda")
@@ -210,10 +335,15 @@ def main():
         out["cpu_baseline"] = cpu_baseline(inst)
         log(f"cpu oracle {out['cpu_baseline']['value']:.3f} it/s")
 
+    del C, p, q
+    torch.cuda.empty_cache()
+    if not args.no_precision:
+        out["precision"] = precision_section(ctx)
+    if not args.no_batch:
+        out["batch"] = batch_section(ctx)
+
     # ---- 20000^2 roofline instance ----------------------------------------------
     if not args.no_large and args.large > 0:
-        del C, p, q
-        torch.cuda.empty_cache()
         L = args.large
         linst = make_instance(L, L, upcast=False)
         C, p, q = upload(linst)

@@ -48,6 +48,9 @@ __all__ = [
     "round_to",
     "rho_runtime",
     "rho_accuracy",
+    "config_batch",
+    "grid_cost",
+    "grid_histogram_pair",
 ]
 
 
@@ -284,3 +287,52 @@ def round_to(inst: Instance, dtype) -> Instance:
     out = Instance(C, p, q, inst.rho, inst.tol, inst.name + f"@{dt.name}", inst.xs, inst.xt,
                    inst.cscale, dict(inst.meta))
     return out
+
+
+def config_batch(count: int = 512, lo: int = 64, hi: int = 2048, seed: int = 0) -> list:
+    """Ragged batch: m and n each uniform in [lo, hi]; each side a 2-D cloud of
+    1-5 Gaussian blobs (sigma 0.1, means uniform in [0,1]^2); squared-Euclidean
+    cost normalised to max 1; Dirichlet(1) marginals; rho0 = 1/ln m; tol 1e-4."""
+    out = []
+    for b in range(count):
+        rng = np.random.default_rng([4, seed, b])
+        m = int(rng.integers(lo, hi + 1))
+        n = int(rng.integers(lo, hi + 1))
+        xs = gaussian_mixture_points(rng, m, 2, int(rng.integers(1, 6)), 0.1)
+        xt = gaussian_mixture_points(rng, n, 2, int(rng.integers(1, 6)), 0.1)
+        C, sc = sq_euclid_cost(xs, xt)
+        p = dirichlet1(rng, m)
+        q = dirichlet1(rng, n)
+        out.append(Instance(C, p, q, rho_runtime(m, n), 1e-4, f"batch[{seed},{b}:{m}x{n}]",
+                            xs, xt, sc))
+    return out
+
+
+GRID = 32
+
+
+def grid_cost(side: int = GRID) -> np.ndarray:
+    """Squared distance between the cells of a side x side grid, divided by its
+    maximum 2 (side-1)^2 (1922 for the 32 x 32 grid)."""
+    ij = np.stack(np.meshgrid(np.arange(side), np.arange(side), indexing="ij"), -1).reshape(-1, 2)
+    D = ((ij[:, None, :] - ij[None, :, :]) ** 2).sum(-1).astype(np.float64)
+    return D / D.max()
+
+
+def _bumps(rng, side: int) -> np.ndarray:
+    ij = np.stack(np.meshgrid(np.arange(side), np.arange(side), indexing="ij"), -1).reshape(-1, 2)
+    h = np.zeros(side * side)
+    for _ in range(int(rng.integers(1, 5))):
+        c = rng.uniform(0, side, 2)
+        w = rng.uniform(1.0, 6.0)
+        a = rng.uniform(0.5, 1.5)
+        h += a * np.exp(-((ij - c) ** 2).sum(-1) / (2 * w * w))
+    return quantise_marginal(h)
+
+
+def grid_histogram_pair(i: int, split: int = 0, side: int = GRID):
+    """(p, q): two histograms on a side x side grid, each a sum of 1-4 Gaussian
+    bumps (centres uniform on the grid, standard deviations 1-6 cells,
+    amplitudes U(0.5, 1.5)), normalised to 1.  split 0 = training, 1 = held out."""
+    rng = np.random.default_rng([5, split, i])
+    return _bumps(rng, side), _bumps(rng, side)

@@ -231,6 +231,62 @@ int drot_solve_cost(drot_ctx *ctx, int64_t m, int64_t n, int dtype, const drot_c
                     int64_t ldx, double *mu, double *nu, const double *mu0, const double *nu0,
                     drot_result *out, void *stream);
 
+/* ---- many independent problems at once ------------------------------ */
+
+/* One problem of a batch: dense cost, in the batch's dtype.  Arrays are
+ * device pointers owned by the caller; mu and nu are optional outputs. */
+typedef struct {
+  int64_t m, n;
+  const void *C;
+  int64_t ldc;
+  const void *p, *q;
+  void *X;            /* out: X_K of this problem (X_0 = p q^T) */
+  int64_t ldx;
+  double rho, tol;    /* per-problem penalty and tolerance */
+  double *mu, *nu;    /* out (nullable): double, length m and n */
+  const double *mu0, *nu0;  /* warm start (nullable, both or neither), as in drot_solve */
+} drot_problem;
+
+/* Solve `count` independent problems of any shapes together: every iteration
+ * is one batched sweep and one batched aux launch over the (problem, tile)
+ * work items of the problems still running, replayed as hipGraphs of
+ * params->check_every iterations.  Each problem runs Algorithm 1 with its own
+ * stopping test and stops on its own; finished problems leave the work lists
+ * when they make up half of them.  params supplies max_iter, tol_mode,
+ * check_every, cache_mode, tile_rows, tile_chunks and DROT_FLAG_NO_GRAPH; one
+ * tile variant serves the whole batch.  outs[count] receives one result per
+ * problem.  Returns DROT_OK when every problem met its test, DROT_MAXITER if
+ * some hit max_iter, or an error (the message names the problem).  The call
+ * uses the context's workspace and releases a problem bound by drot_bind. */
+int drot_solve_batched(drot_ctx *ctx, int32_t count, int dtype, const drot_problem *probs,
+                       const drot_params *params, drot_result *outs, void *stream);
+
+/* ---- learned warm start: a small MLP trained with this library's kernels ---
+ * Not part of the paper: a network maps (p, q) to initial dual variables
+ * (mu, nu); DROT then starts from phi_0 = rho mu, psi_0 = rho nu (drot_solve's
+ * mu0/nu0), which is valid because DR converges from any start (Lemma 1).
+ * Architecture in -> hidden (ReLU) -> hidden (ReLU) -> out, mean-squared
+ * error.  Float32 master weights and Adam; bfloat16 copies feed the matrix
+ * cores (32x32x8 bfloat16 MFMA, float32 accumulation).  Widths and batches
+ * are multiples of 64.  The flat parameter vector is [W1, b1, W2, b2, W3, b3]
+ * with W_l stored row-major as out_l x in_l.  x, y, t and grad are device
+ * float32 arrays, row-major batch x width. */
+typedef struct drot_mlp drot_mlp;
+int drot_mlp_create(drot_mlp **mlp, int device, int in_dim, int hidden, int out_dim,
+                    int max_batch, uint64_t seed);
+int drot_mlp_destroy(drot_mlp *mlp);
+int drot_mlp_num_params(const drot_mlp *mlp, int64_t *count);
+int drot_mlp_set_weights(drot_mlp *mlp, const float *host);  /* also resets Adam */
+int drot_mlp_get_weights(drot_mlp *mlp, float *host);
+int drot_mlp_forward(drot_mlp *mlp, int batch, const float *x, float *y, void *stream);
+/* Loss (host, FP64-accumulated mean squared error) and its gradient w.r.t.
+ * the flat parameters (grad may be NULL). */
+int drot_mlp_gradients(drot_mlp *mlp, int batch, const float *x, const float *t, float *grad,
+                       double *loss, void *stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the batch's loss. */
+int drot_mlp_train_step(drot_mlp *mlp, int batch, const float *x, const float *t, float lr,
+                        double *loss, void *stream);
+
 /* Copy per-iteration records of the last bound problem to host memory.
  * Record k (1-based iteration index) holds 8 doubles:
  *   pobj, dobj, r_primal, r_dual (lagged, see drot_tol_mode), gap,

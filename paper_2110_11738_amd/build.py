@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libdrot.so")
-SOURCES = ["drot_kernels.hip", "drot_host.hip"]
+SOURCES = ["drot_kernels.hip", "drot_host.hip", "drot_batch.hip", "drot_mlp.hip"]
 ARCH = "gfx950"
 
 

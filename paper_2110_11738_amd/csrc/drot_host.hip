@@ -397,6 +397,37 @@ int check_ctx(drot_ctx* c) {
 
 }  // namespace
 
+// Helpers for the batched driver (drot_batch.hip).
+int drot_internal_fail(int code, const char* msg) { return fail(code, "%s", msg); }
+
+double drot_internal_wall_rate(const drot_ctx* c) { return c->wall_rate; }
+
+// Make the context's workspace at least `bytes` large for a batched solve.
+// The single-problem binding lives in the same workspace and is released.
+int drot_internal_ctx_prepare(drot_ctx* c, void** ws, size_t bytes) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  drop_graph(c);
+  c->bound = false;
+  if (bytes > c->ws_bytes) {
+    if (c->ws) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(c->ws);
+      c->ws = nullptr;
+      c->ws_bytes = 0;
+    }
+    const size_t want = bytes + bytes / 4;
+    if (hipMalloc(&c->ws, want) != hipSuccess) {
+      (void)hipGetLastError();
+      c->ws = nullptr;
+      return fail(DROT_ENOMEM, "workspace allocation of %zu bytes failed", want);
+    }
+    c->ws_bytes = want;
+  }
+  *ws = c->ws;
+  return DROT_OK;
+}
+
 extern "C" {
 
 const char* drot_version(void) { return "drot-mi355x 0.1.0 (gfx950)"; }
@@ -507,6 +538,7 @@ int drot_bind_cost(drot_ctx* c, int64_t m, int64_t n, int dtype, const drot_cost
   sa.nu0 = nu0;
   sa.st = c->st;
   sa.trace = c->trace;
+  sa.trace_cap = kTraceCap;
   sa.wall_rate = c->wall_rate;
   sa.g = g.g;
 

@@ -17,7 +17,7 @@ constexpr int kTraceWidth = 8;
 constexpr int kAuxCols = 32;       // columns per aux workgroup
 
 // Workgroups of one aux launch: column groups of kAuxCols, then rows by kBlock.
-inline int64_t aux_workgroups(int64_t m, int64_t n) {
+__host__ __device__ inline int64_t aux_workgroups(int64_t m, int64_t n) {
   return (n + kAuxCols - 1) / kAuxCols + (m + kBlock - 1) / kBlock;
 }
 
@@ -126,7 +126,8 @@ struct SweepArgs {
   void* rowpart;           // [n_ct][m]
   double* tiles;           // [n_rg * n_ct][kTileSlots], workgroup (g, ct) at g * n_ct + ct
   double* blockpart;       // [aux workgroups][kSlots]
-  double* trace;           // [kTraceCap][kTraceWidth]
+  double* trace;           // [trace_cap][kTraceWidth]
+  int64_t trace_cap;       // records kept (ring)
   double wall_rate;        // wall_clock64 ticks per second
   SweepGeom g;
 };
@@ -148,5 +149,13 @@ hipError_t launch_sweep(int dtype, int mode, const TileCfg& t, const SweepArgs& 
 hipError_t launch_aux(int dtype, int mode, const SweepArgs& a, hipStream_t s);
 hipError_t launch_prep(const SweepArgs& a, hipStream_t s);
 hipError_t launch_maxc(const SweepArgs& a, hipStream_t s);
+
+// Batched problems: `args` (device) holds one SweepArgs per problem; the work
+// lists hold (problem, workgroup) pairs for the sweep and the aux kernel of
+// one iteration (dense cost, 4 rows in flight).
+hipError_t launch_batch_step(int dtype, int mode, const TileCfg& t, const SweepArgs* args,
+                             const uint2* sweep_work, int64_t n_sweep, const uint2* aux_work,
+                             int64_t n_aux, hipStream_t s);
+hipError_t launch_prep_batch(const SweepArgs* args, int count, hipStream_t s);
 
 }  // namespace drot

@@ -251,7 +251,7 @@ __device__ void finish_global(const SweepArgs& a, int nb, double (&red)[kSlots][
     st->rd = rd;
     st->gap = gap;
     st->test = test;
-    double* tr = a.trace + ((k - 1) % kTraceCap) * kTraceWidth;
+    double* tr = a.trace + ((k - 1) % a.trace_cap) * kTraceWidth;
     tr[0] = pobj;
     tr[1] = dobj;
     tr[2] = rp;
@@ -315,7 +315,7 @@ __device__ void finish_global(const SweepArgs& a, int nb, double (&red)[kSlots][
 // the tile scalars.  The last workgroup to finish does the scalar steps.
 // ---------------------------------------------------------------------------
 template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void aux_kernel(SweepArgs a) {
+__device__ __forceinline__ void aux_body(const SweepArgs& a, const int b, const int nb) {
   using P = typename PartialOf<T, MODE>::type;
   constexpr int CW = 16 / sizeof(P);      // columns per 16-byte chunk
   constexpr int NCH = kAuxCols / CW;      // chunks per workgroup
@@ -334,8 +334,6 @@ __global__ __launch_bounds__(kBlock) void aux_kernel(SweepArgs a) {
   for (int s = 0; s < kSlots; ++s) acc[s] = 0.0;
   const int64_t m = a.g.m, n = a.g.n;
   const int col_wgs = (int)((n + kAuxCols - 1) / kAuxCols);
-  const int b = blockIdx.x;
-  const int nb = gridDim.x;
   const double rho = st->rho;
 
   if (b < col_wgs) {
@@ -454,6 +452,20 @@ __global__ __launch_bounds__(kBlock) void aux_kernel(SweepArgs a) {
     __hip_atomic_store(&st->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void aux_kernel(SweepArgs a) {
+  aux_body<T, MODE>(a, blockIdx.x, gridDim.x);
+}
+
+// Batched form: work item = (problem, aux workgroup of that problem).
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void aux_batch_kernel(const SweepArgs* __restrict__ args,
+                                                           const uint2* __restrict__ work) {
+  const uint2 w = work[blockIdx.x];
+  const SweepArgs& a = args[w.x];
+  aux_body<T, MODE>(a, (int)w.y, (int)aux_workgroups(a.g.m, a.g.n));
+}
+
 // ---------------------------------------------------------------------------
 // The sweep.  A workgroup owns one column strip of W = 64 * VEC * CH columns
 // and the row blocks g, g + G, g + 2G, ... of `rows` rows each (G = n_rg row
@@ -465,7 +477,7 @@ __global__ __launch_bounds__(kBlock) void aux_kernel(SweepArgs a) {
 // flight.  Consecutive workgroups take consecutive strips of the same group.
 // ---------------------------------------------------------------------------
 template <typename T, int MODE, int VEC, int CH, int U, bool NT, int CM, int D, bool RAGGED>
-__global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a) {
+__device__ __forceinline__ void sweep_body(const SweepArgs& a, const int ct, const int rg) {
   using P = typename PartialOf<T, MODE>::type;
   using A = typename std::conditional<is_final(MODE), double, T>::type;
   constexpr int CPL = VEC * CH;
@@ -480,8 +492,6 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a) {
 
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int ct = blockIdx.x % a.g.n_ct;
-  const int rg = blockIdx.x / a.g.n_ct;
   const int64_t m = a.g.m, n = a.g.n;
   const int64_t col0 = (int64_t)ct * W;
   const int rpw = (a.g.rows + kWaves - 1) / kWaves;
@@ -705,9 +715,25 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a) {
   }
 }
 
+template <typename T, int MODE, int VEC, int CH, int U, bool NT, int CM, int D, bool RAGGED>
+__global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a) {
+  sweep_body<T, MODE, VEC, CH, U, NT, CM, D, RAGGED>(a, blockIdx.x % a.g.n_ct,
+                                                      blockIdx.x / a.g.n_ct);
+}
+
+// Batched form: work item = (problem, workgroup of that problem's sweep).
+template <typename T, int MODE, int VEC, int CH, bool NT, bool RAGGED>
+__global__ __launch_bounds__(kBlock) void sweep_batch_kernel(const SweepArgs* __restrict__ args,
+                                                             const uint2* __restrict__ work) {
+  const uint2 w = work[blockIdx.x];
+  const SweepArgs& a = args[w.x];
+  sweep_body<T, MODE, VEC, CH, 4, NT, kCostDense, 1, RAGGED>(a, (int)(w.y % a.g.n_ct),
+                                                              (int)(w.y / a.g.n_ct));
+}
+
 // Warm-start sums sum(phi_0) = rho sum(mu0), sum(psi_0) = rho sum(nu0), the
 // start timestamp, and zeroed completion counters.  One workgroup.
-__global__ __launch_bounds__(kBlock) void prep_kernel(SweepArgs a) {
+__device__ __forceinline__ void prep_body(const SweepArgs& a) {
   __shared__ double red[kSlots][kWaves];
   double acc[kSlots];
 #pragma unroll
@@ -730,6 +756,12 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(SweepArgs a) {
     st->t_last = st->t_start;
     st->counter = 0;
   }
+}
+
+__global__ __launch_bounds__(kBlock) void prep_kernel(SweepArgs a) { prep_body(a); }
+
+__global__ __launch_bounds__(kBlock) void prep_batch_kernel(const SweepArgs* __restrict__ args) {
+  prep_body(args[blockIdx.x]);
 }
 
 template <typename T, int MODE, int VEC, int CH, int U, bool NT, int CM = kCostDense, int D = 1,
@@ -895,6 +927,67 @@ hipError_t launch_aux(int dtype, int mode, const SweepArgs& a, hipStream_t s) {
 hipError_t launch_sweep(int dtype, int mode, const TileCfg& t, const SweepArgs& a,
                         hipStream_t s) {
   return dtype == 0 ? sweep_type<float>(mode, t, a, s) : sweep_type<double>(mode, t, a, s);
+}
+
+namespace {
+
+template <typename T, int MODE>
+hipError_t sweep_batch_mode(const TileCfg& t, const SweepArgs* args, const uint2* work,
+                            int64_t nwork, hipStream_t s) {
+  constexpr int V = 16 / sizeof(T);
+  const dim3 grid((unsigned)nwork), block(kBlock);
+  if (t.vec == 1 && t.chunks == 4) {
+    hipLaunchKernelGGL((sweep_batch_kernel<T, MODE, 1, 4, false, false>), grid, block, 0, s, args, work);
+    return hipGetLastError();
+  }
+  if (t.vec != V || t.unroll != 4) return hipErrorInvalidValue;
+  switch ((t.chunks == 2 ? 1 : 0) | (t.stream ? 2 : 0)) {
+    case 0: hipLaunchKernelGGL((sweep_batch_kernel<T, MODE, V, 1, false, true>), grid, block, 0, s, args, work); break;
+    case 1: hipLaunchKernelGGL((sweep_batch_kernel<T, MODE, V, 2, false, true>), grid, block, 0, s, args, work); break;
+    case 2: hipLaunchKernelGGL((sweep_batch_kernel<T, MODE, V, 1, true, true>), grid, block, 0, s, args, work); break;
+    case 3: hipLaunchKernelGGL((sweep_batch_kernel<T, MODE, V, 2, true, true>), grid, block, 0, s, args, work); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t batch_type(int mode, const TileCfg& t, const SweepArgs* args, const uint2* sweep_work,
+                      int64_t n_sweep, const uint2* aux_work, int64_t n_aux, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  const dim3 ag((unsigned)n_aux), block(kBlock);
+  switch (mode) {
+    case kIter:
+      e = sweep_batch_mode<T, kIter>(t, args, sweep_work, n_sweep, s);
+      if (e == hipSuccess) hipLaunchKernelGGL((aux_batch_kernel<T, kIter>), ag, block, 0, s, args, aux_work);
+      break;
+    case kInitPQ:
+    case kInitX:
+      e = mode == kInitPQ ? sweep_batch_mode<T, kInitPQ>(t, args, sweep_work, n_sweep, s)
+                          : sweep_batch_mode<T, kInitX>(t, args, sweep_work, n_sweep, s);
+      if (e == hipSuccess) hipLaunchKernelGGL((aux_batch_kernel<T, kInitPQ>), ag, block, 0, s, args, aux_work);
+      break;
+    case kFinal:
+      e = sweep_batch_mode<T, kFinal>(t, args, sweep_work, n_sweep, s);
+      if (e == hipSuccess) hipLaunchKernelGGL((aux_batch_kernel<T, kFinal>), ag, block, 0, s, args, aux_work);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return e != hipSuccess ? e : hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_batch_step(int dtype, int mode, const TileCfg& t, const SweepArgs* args,
+                             const uint2* sweep_work, int64_t n_sweep, const uint2* aux_work,
+                             int64_t n_aux, hipStream_t s) {
+  if (n_sweep <= 0 || n_aux <= 0) return hipSuccess;
+  return dtype == 0 ? batch_type<float>(mode, t, args, sweep_work, n_sweep, aux_work, n_aux, s)
+                    : batch_type<double>(mode, t, args, sweep_work, n_sweep, aux_work, n_aux, s);
+}
+
+hipError_t launch_prep_batch(const SweepArgs* args, int count, hipStream_t s) {
+  hipLaunchKernelGGL(prep_batch_kernel, dim3((unsigned)count), dim3(kBlock), 0, s, args);
+  return hipGetLastError();
 }
 
 hipError_t launch_maxc(const SweepArgs& a, hipStream_t s) {

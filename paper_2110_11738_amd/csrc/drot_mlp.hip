@@ -1,0 +1,438 @@
+// A small multilayer perceptron trained with hand-written gfx950 kernels:
+// the learned warm start of DROT.  It maps the marginals (p, q) of an OT
+// problem to initial dual variables (mu, nu); DROT then starts from the shifts
+// phi_0 = rho mu, psi_0 = rho nu (a warm start is valid because DR converges
+// from any starting point, Lemma 1).
+//
+// Network: in -> hidden (ReLU) -> hidden (ReLU) -> out, mean-squared-error
+// loss.  Weights are kept in float32 (Adam master copy) and bfloat16 (the
+// copy the matrix cores read); activations and gradients enter the GEMMs in
+// bfloat16 and every GEMM accumulates in float32 on the MFMA units
+// (v_mfma_f32_32x32x8 bf16).  All reductions run in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/drot.h"
+
+int drot_internal_fail(int code, const char* msg);
+
+namespace {
+
+int mfail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  return drot_internal_fail(code, buf);
+}
+
+#define MHIP(expr)                                                                   \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return mfail(DROT_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+  } while (0)
+
+typedef uint16_t bf16;
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+__host__ __device__ inline bf16 to_bf16(float f) {
+  // round to nearest even (finite inputs)
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (bf16)(u >> 16);
+}
+
+__device__ inline float from_bf16(bf16 b) { return __uint_as_float((uint32_t)b << 16); }
+
+// ---------------------------------------------------------------------------
+// C[M x N] = alpha * op(A)[M x K] * op(B)[K x N] + beta * C, bfloat16 inputs,
+// float32 accumulation and output.  A is stored row-major as M x K (TA = 0)
+// or K x M (TA = 1); B as K x N (TB = 0) or N x K (TB = 1).  A workgroup of
+// four waves computes a 64 x 64 tile, each wave a 32 x 32 block with the
+// 32x32x8 bfloat16 MFMA; K advances 32 at a time through LDS.
+// Requires M % 64 == N % 64 == K % 32 == 0 (checked on the host).
+// ---------------------------------------------------------------------------
+template <int TA, int TB>
+__global__ __launch_bounds__(256) void gemm_bf16(const bf16* __restrict__ A, const bf16* __restrict__ B,
+                                                 float* __restrict__ C, int M, int N, int K, int lda,
+                                                 int ldb, int ldc, float alpha, float beta) {
+  __shared__ bf16 As[64][32 + 4];
+  __shared__ bf16 Bs[32][64 + 4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int wr = wave >> 1, wc = wave & 1;
+  v16f acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    // 64 x 32 A tile and 32 x 64 B tile, 8 elements per thread each.
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int e = tid + 256 * t;  // 0..2047
+      const int r = e >> 5, c = e & 31;         // A tile (row r of 64, col c of 32)
+      As[r][c] = TA ? A[(size_t)(k0 + c) * lda + (m0 + r)] : A[(size_t)(m0 + r) * lda + (k0 + c)];
+      const int br = e >> 6, bc = e & 63;       // B tile (row br of 32, col bc of 64)
+      Bs[br][bc] = TB ? B[(size_t)(n0 + bc) * ldb + (k0 + br)] : B[(size_t)(k0 + br) * ldb + (n0 + bc)];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 32; kk += 8) {
+      v4s a, b;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[i] = (short)As[wr * 32 + (lane & 31)][kk + 4 * (lane >> 5) + i];
+        b[i] = (short)Bs[kk + 4 * (lane >> 5) + i][wc * 32 + (lane & 31)];
+      }
+      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // lane holds column (lane % 32) and rows 8 (r / 4) + 4 (lane / 32) + r % 4
+  const int col = n0 + wc * 32 + (lane & 31);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = m0 + wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    float* out = C + (size_t)row * ldc + col;
+    *out = alpha * acc[r] + (beta != 0.f ? beta * *out : 0.f);
+  }
+}
+
+// y = act(z + bias) in float32, plus its bfloat16 copy.
+__global__ void bias_act(const float* __restrict__ z, const float* __restrict__ bias,
+                         float* __restrict__ y, bf16* __restrict__ yb, int rows, int cols, int relu) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)rows * cols) return;
+  float v = z[i] + bias[i % cols];
+  if (relu && !(v > 0.f)) v = 0.f;
+  y[i] = v;
+  yb[i] = to_bf16(v);
+}
+
+// dz = dh * [a > 0] (ReLU backward), float32 and bfloat16.
+__global__ void relu_back(const float* __restrict__ dh, const float* __restrict__ a,
+                          float* __restrict__ dz, bf16* __restrict__ dzb, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float v = a[i] > 0.f ? dh[i] : 0.f;
+  dz[i] = v;
+  dzb[i] = to_bf16(v);
+}
+
+// Mean squared error: dy = 2 (y - t) / count; per-block partial sums of
+// (y - t)^2 in float64 (fixed order), summed by the host.
+__global__ void mse_grad(const float* __restrict__ y, const float* __restrict__ t,
+                         float* __restrict__ dy, bf16* __restrict__ dyb, double* __restrict__ part,
+                         int64_t count) {
+  __shared__ double red[256];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double s = 0.0;
+  if (i < count) {
+    const float d = y[i] - t[i];
+    const float g = 2.f * d / (float)count;
+    dy[i] = g;
+    dyb[i] = to_bf16(g);
+    s = (double)d * (double)d;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// Column sums of a rows x cols float32 matrix (bias gradients), fixed order.
+__global__ void col_sum(const float* __restrict__ g, float* __restrict__ out, int rows, int cols) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cols) return;
+  float s = 0.f;
+  for (int r = 0; r < rows; ++r) s += g[(int64_t)r * cols + j];
+  out[j] = s;
+}
+
+__global__ void cast_bf16(const float* __restrict__ x, bf16* __restrict__ y, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) y[i] = to_bf16(x[i]);
+}
+
+// Adam on the float32 master weights; refreshes the bfloat16 copy.
+__global__ void adam(float* __restrict__ w, bf16* __restrict__ wb, const float* __restrict__ g,
+                     float* __restrict__ m1, float* __restrict__ m2, int64_t count, float lr,
+                     float b1, float b2, float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float gi = g[i];
+  const float a = b1 * m1[i] + (1.f - b1) * gi;
+  const float b = b2 * m2[i] + (1.f - b2) * gi * gi;
+  m1[i] = a;
+  m2[i] = b;
+  const float v = w[i] - lr * (a / c1) / (sqrtf(b / c2) + eps);
+  w[i] = v;
+  wb[i] = to_bf16(v);
+}
+
+unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+struct drot_mlp {
+  int device = 0;
+  int in = 0, hid = 0, out = 0, max_batch = 0;
+  int64_t n_params = 0;
+  int64_t off_w[3], off_b[3];  // offsets into the flat parameter vector
+  // device buffers
+  float* w = nullptr;    // float32 master parameters (flat)
+  bf16* wb = nullptr;    // bfloat16 copy
+  float* g = nullptr;    // gradients (flat)
+  float* m1 = nullptr;
+  float* m2 = nullptr;
+  float *z[3] = {}, *a[3] = {};  // pre-activations (GEMM out) and activations
+  bf16 *ab[3] = {}, *xb = nullptr;
+  float *d[3] = {}, *dh = nullptr;
+  bf16 *db[3] = {};
+  double* part = nullptr;
+  double* part_host = nullptr;
+  int64_t step = 0;
+};
+
+namespace {
+
+int64_t layer_in(const drot_mlp* n, int l) { return l == 0 ? n->in : n->hid; }
+int64_t layer_out(const drot_mlp* n, int l) { return l == 2 ? n->out : n->hid; }
+
+hipError_t gemm(const bf16* A, const bf16* B, float* C, int M, int N, int K, int lda, int ldb,
+                int ldc, int ta, int tb, float beta, hipStream_t s) {
+  const dim3 grid(N / 64, M / 64), block(256);
+  if (!ta && !tb) hipLaunchKernelGGL((gemm_bf16<0, 0>), grid, block, 0, s, A, B, C, M, N, K, lda, ldb, ldc, 1.f, beta);
+  if (!ta && tb) hipLaunchKernelGGL((gemm_bf16<0, 1>), grid, block, 0, s, A, B, C, M, N, K, lda, ldb, ldc, 1.f, beta);
+  if (ta && !tb) hipLaunchKernelGGL((gemm_bf16<1, 0>), grid, block, 0, s, A, B, C, M, N, K, lda, ldb, ldc, 1.f, beta);
+  if (ta && tb) hipLaunchKernelGGL((gemm_bf16<1, 1>), grid, block, 0, s, A, B, C, M, N, K, lda, ldb, ldc, 1.f, beta);
+  return hipGetLastError();
+}
+
+int check_batch(const drot_mlp* n, int batch) {
+  if (!n) return mfail(DROT_EINVAL, "mlp is NULL");
+  if (batch < 64 || batch % 64 || batch > n->max_batch)
+    return mfail(DROT_EINVAL, "batch must be a multiple of 64 in [64, %d]", n->max_batch);
+  if (hipSetDevice(n->device) != hipSuccess) return mfail(DROT_EDEVICE, "hipSetDevice failed");
+  return DROT_OK;
+}
+
+int forward(drot_mlp* n, int B, const float* x, hipStream_t s) {
+  hipLaunchKernelGGL(cast_bf16, dim3(nblk((int64_t)B * n->in)), dim3(256), 0, s, x, n->xb,
+                     (int64_t)B * n->in);
+  MHIP(hipGetLastError());
+  const bf16* inp = n->xb;
+  for (int l = 0; l < 3; ++l) {
+    const int K = (int)layer_in(n, l), N = (int)layer_out(n, l);
+    MHIP(gemm(inp, n->wb + n->off_w[l], n->z[l], B, N, K, K, K, N, 0, 1, 0.f, s));
+    hipLaunchKernelGGL(bias_act, dim3(nblk((int64_t)B * N)), dim3(256), 0, s, n->z[l],
+                       n->w + n->off_b[l], n->a[l], n->ab[l], B, N, l < 2 ? 1 : 0);
+    MHIP(hipGetLastError());
+    inp = n->ab[l];
+  }
+  return DROT_OK;
+}
+
+// Gradients of the mean-squared error into n->g; loss to *loss (host).
+int backward(drot_mlp* n, int B, const float* t, double* loss, hipStream_t s) {
+  const int64_t cnt = (int64_t)B * n->out;
+  const unsigned nb = nblk(cnt);
+  hipLaunchKernelGGL(mse_grad, dim3(nb), dim3(256), 0, s, n->a[2], t, n->d[2], n->db[2], n->part, cnt);
+  MHIP(hipGetLastError());
+  for (int l = 2; l >= 0; --l) {
+    const int K = (int)layer_in(n, l), N = (int)layer_out(n, l);
+    const bf16* inp = l == 0 ? n->xb : n->ab[l - 1];
+    // dW_l = dZ_l^T x_l  (N x K);  db_l = column sums of dZ_l
+    MHIP(gemm(n->db[l], inp, n->g + n->off_w[l], N, K, B, N, K, K, 1, 0, 0.f, s));
+    hipLaunchKernelGGL(col_sum, dim3(nblk(N)), dim3(256), 0, s, n->d[l], n->g + n->off_b[l], B, N);
+    MHIP(hipGetLastError());
+    if (l > 0) {
+      // dh_{l-1} = dZ_l W_l (B x K), then through the ReLU of layer l-1
+      MHIP(gemm(n->db[l], n->wb + n->off_w[l], n->dh, B, K, N, N, K, K, 0, 0, 0.f, s));
+      hipLaunchKernelGGL(relu_back, dim3(nblk((int64_t)B * K)), dim3(256), 0, s, n->dh,
+                         n->a[l - 1], n->d[l - 1], n->db[l - 1], (int64_t)B * K);
+      MHIP(hipGetLastError());
+    }
+  }
+  MHIP(hipMemcpyAsync(n->part_host, n->part, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+  MHIP(hipStreamSynchronize(s));
+  double acc = 0.0;
+  for (unsigned k = 0; k < nb; ++k) acc += n->part_host[k];
+  if (loss) *loss = acc / (double)cnt;
+  return DROT_OK;
+}
+
+uint64_t splitmix(uint64_t& s) {
+  uint64_t z = (s += 0x9e3779b97f4a7c15ull);
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+}  // namespace
+
+extern "C" {
+
+int drot_mlp_create(drot_mlp** out, int device, int in, int hidden, int outd, int max_batch,
+                    uint64_t seed) {
+  if (!out) return mfail(DROT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (in < 64 || hidden < 64 || outd < 64 || in % 64 || hidden % 64 || outd % 64)
+    return mfail(DROT_EINVAL, "layer widths must be positive multiples of 64");
+  if (max_batch < 64 || max_batch % 64) return mfail(DROT_EINVAL, "max_batch must be a multiple of 64");
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+    (void)hipGetLastError();
+    return mfail(DROT_EDEVICE, "no HIP device available");
+  }
+  if (device < 0 || device >= count) return mfail(DROT_EINVAL, "device out of range");
+  MHIP(hipSetDevice(device));
+  drot_mlp* n = new drot_mlp();
+  n->device = device;
+  n->in = in;
+  n->hid = hidden;
+  n->out = outd;
+  n->max_batch = max_batch;
+  int64_t o = 0;
+  for (int l = 0; l < 3; ++l) {
+    n->off_w[l] = o;
+    o += layer_in(n, l) * layer_out(n, l);
+    n->off_b[l] = o;
+    o += layer_out(n, l);
+  }
+  n->n_params = o;
+  // He-uniform initialisation from a seeded counter-based generator.
+  std::vector<float> hw(o, 0.f);
+  uint64_t st = seed;
+  for (int l = 0; l < 3; ++l) {
+    const double lim = std::sqrt(6.0 / (double)layer_in(n, l));
+    for (int64_t k = 0; k < layer_in(n, l) * layer_out(n, l); ++k) {
+      const double u = (double)(splitmix(st) >> 11) * (1.0 / 9007199254740992.0);
+      hw[n->off_w[l] + k] = (float)((2.0 * u - 1.0) * lim);
+    }
+  }
+  bool ok = hipMalloc(&n->w, sizeof(float) * o) == hipSuccess &&
+            hipMalloc(&n->wb, sizeof(bf16) * o) == hipSuccess &&
+            hipMalloc(&n->g, sizeof(float) * o) == hipSuccess &&
+            hipMalloc(&n->m1, sizeof(float) * o) == hipSuccess &&
+            hipMalloc(&n->m2, sizeof(float) * o) == hipSuccess &&
+            hipMalloc(&n->xb, sizeof(bf16) * (size_t)max_batch * in) == hipSuccess &&
+            hipMalloc(&n->dh, sizeof(float) * (size_t)max_batch * hidden) == hipSuccess &&
+            hipMalloc(&n->part, sizeof(double) * nblk((int64_t)max_batch * outd)) == hipSuccess &&
+            hipHostMalloc((void**)&n->part_host, sizeof(double) * nblk((int64_t)max_batch * outd),
+                          hipHostMallocDefault) == hipSuccess;
+  for (int l = 0; l < 3 && ok; ++l) {
+    const size_t c = (size_t)max_batch * layer_out(n, l);
+    ok = hipMalloc(&n->z[l], sizeof(float) * c) == hipSuccess &&
+         hipMalloc(&n->a[l], sizeof(float) * c) == hipSuccess &&
+         hipMalloc(&n->ab[l], sizeof(bf16) * c) == hipSuccess &&
+         hipMalloc(&n->d[l], sizeof(float) * c) == hipSuccess &&
+         hipMalloc(&n->db[l], sizeof(bf16) * c) == hipSuccess;
+  }
+  if (!ok) {
+    (void)hipGetLastError();
+    drot_mlp_destroy(n);
+    return mfail(DROT_ENOMEM, "MLP allocation failed");
+  }
+  if (drot_mlp_set_weights(n, hw.data()) != DROT_OK) {
+    drot_mlp_destroy(n);
+    return DROT_EDEVICE;
+  }
+  *out = n;
+  return DROT_OK;
+}
+
+int drot_mlp_destroy(drot_mlp* n) {
+  if (!n) return DROT_OK;
+  (void)hipSetDevice(n->device);
+  (void)hipDeviceSynchronize();
+  void* bufs[] = {n->w, n->wb, n->g, n->m1, n->m2, n->xb, n->dh, n->part};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  for (int l = 0; l < 3; ++l) {
+    void* lb[] = {n->z[l], n->a[l], n->ab[l], n->d[l], n->db[l]};
+    for (void* b : lb)
+      if (b) (void)hipFree(b);
+  }
+  if (n->part_host) (void)hipHostFree(n->part_host);
+  delete n;
+  return DROT_OK;
+}
+
+int drot_mlp_num_params(const drot_mlp* n, int64_t* count) {
+  if (!n || !count) return mfail(DROT_EINVAL, "NULL argument");
+  *count = n->n_params;
+  return DROT_OK;
+}
+
+int drot_mlp_set_weights(drot_mlp* n, const float* host) {
+  if (!n || !host) return mfail(DROT_EINVAL, "NULL argument");
+  MHIP(hipSetDevice(n->device));
+  MHIP(hipMemcpy(n->w, host, sizeof(float) * n->n_params, hipMemcpyHostToDevice));
+  hipLaunchKernelGGL(cast_bf16, dim3(nblk(n->n_params)), dim3(256), 0, 0, n->w, n->wb, n->n_params);
+  MHIP(hipGetLastError());
+  MHIP(hipMemset(n->m1, 0, sizeof(float) * n->n_params));
+  MHIP(hipMemset(n->m2, 0, sizeof(float) * n->n_params));
+  MHIP(hipDeviceSynchronize());
+  n->step = 0;
+  return DROT_OK;
+}
+
+int drot_mlp_get_weights(drot_mlp* n, float* host) {
+  if (!n || !host) return mfail(DROT_EINVAL, "NULL argument");
+  MHIP(hipSetDevice(n->device));
+  MHIP(hipDeviceSynchronize());
+  MHIP(hipMemcpy(host, n->w, sizeof(float) * n->n_params, hipMemcpyDeviceToHost));
+  return DROT_OK;
+}
+
+int drot_mlp_forward(drot_mlp* n, int batch, const float* x, float* y, void* stream) {
+  int rc = check_batch(n, batch);
+  if (rc) return rc;
+  if (!x || !y) return mfail(DROT_EINVAL, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = forward(n, batch, x, s))) return rc;
+  MHIP(hipMemcpyAsync(y, n->a[2], sizeof(float) * (size_t)batch * n->out, hipMemcpyDeviceToDevice, s));
+  return DROT_OK;
+}
+
+int drot_mlp_gradients(drot_mlp* n, int batch, const float* x, const float* t, float* grad,
+                       double* loss, void* stream) {
+  int rc = check_batch(n, batch);
+  if (rc) return rc;
+  if (!x || !t) return mfail(DROT_EINVAL, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = forward(n, batch, x, s))) return rc;
+  if ((rc = backward(n, batch, t, loss, s))) return rc;
+  if (grad) MHIP(hipMemcpyAsync(grad, n->g, sizeof(float) * n->n_params, hipMemcpyDeviceToDevice, s));
+  return DROT_OK;
+}
+
+int drot_mlp_train_step(drot_mlp* n, int batch, const float* x, const float* t, float lr,
+                        double* loss, void* stream) {
+  int rc = drot_mlp_gradients(n, batch, x, t, nullptr, loss, stream);
+  if (rc) return rc;
+  if (!(lr > 0.f)) return mfail(DROT_EINVAL, "lr must be positive");
+  hipStream_t s = (hipStream_t)stream;
+  n->step += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - std::pow(b1, (float)n->step), c2 = 1.f - std::pow(b2, (float)n->step);
+  hipLaunchKernelGGL(adam, dim3(nblk(n->n_params)), dim3(256), 0, s, n->w, n->wb, n->g, n->m1,
+                     n->m2, n->n_params, lr, b1, b2, 1e-8f, c1, c2);
+  MHIP(hipGetLastError());
+  return DROT_OK;
+}
+
+}  // extern "C"

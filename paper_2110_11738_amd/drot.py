@@ -29,7 +29,10 @@ TRACE_FIELDS = ("pobj", "dobj", "r_primal", "r_dual_lag", "gap", "test", "second
 
 EXPORTED = ("drot_version", "drot_strerror", "drot_last_error", "drot_ctx_create",
             "drot_ctx_destroy", "drot_solve", "drot_bind", "drot_iterate", "drot_poll",
-            "drot_finish", "drot_get_trace", "drot_bind_cost", "drot_solve_cost")
+            "drot_finish", "drot_get_trace", "drot_bind_cost", "drot_solve_cost",
+            "drot_solve_batched", "drot_mlp_create", "drot_mlp_destroy", "drot_mlp_num_params",
+            "drot_mlp_set_weights", "drot_mlp_get_weights", "drot_mlp_forward",
+            "drot_mlp_gradients", "drot_mlp_train_step")
 
 
 class Params(ctypes.Structure):
@@ -60,6 +63,14 @@ class Cost(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("dim", ctypes.c_int32), ("data", ctypes.c_void_p),
                 ("ld", ctypes.c_int64), ("xs", ctypes.c_void_p), ("xt", ctypes.c_void_p),
                 ("scale", ctypes.c_double)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("C", ctypes.c_void_p),
+                ("ldc", ctypes.c_int64), ("p", ctypes.c_void_p), ("q", ctypes.c_void_p),
+                ("X", ctypes.c_void_p), ("ldx", ctypes.c_int64), ("rho", ctypes.c_double),
+                ("tol", ctypes.c_double), ("mu", ctypes.c_void_p), ("nu", ctypes.c_void_p),
+                ("mu0", ctypes.c_void_p), ("nu0", ctypes.c_void_p)]
 
 
 class DrotError(RuntimeError):
@@ -98,6 +109,18 @@ def lib():
                    i64]
     L.drot_bind_cost.argtypes = cost_common + [vp, vp, vp]
     L.drot_solve_cost.argtypes = cost_common + [vp, vp, vp, vp, ctypes.POINTER(Result), vp]
+    L.drot_solve_batched.argtypes = [vp, ctypes.c_int32, i32, ctypes.POINTER(Problem),
+                                     ctypes.POINTER(Params), ctypes.POINTER(Result), vp]
+    fp = ctypes.POINTER(ctypes.c_float)
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.drot_mlp_create.argtypes = [ctypes.POINTER(vp), i32, i32, i32, i32, i32, ctypes.c_uint64]
+    L.drot_mlp_destroy.argtypes = [vp]
+    L.drot_mlp_num_params.argtypes = [vp, ctypes.POINTER(i64)]
+    L.drot_mlp_set_weights.argtypes = [vp, fp]
+    L.drot_mlp_get_weights.argtypes = [vp, fp]
+    L.drot_mlp_forward.argtypes = [vp, i32, vp, vp, vp]
+    L.drot_mlp_gradients.argtypes = [vp, i32, vp, vp, vp, dp, vp]
+    L.drot_mlp_train_step.argtypes = [vp, i32, vp, vp, ctypes.c_float, dp, vp]
     for name in EXPORTED:
         getattr(L, name).restype = getattr(L, name).restype or i32
     _lib = L
@@ -270,6 +293,118 @@ def solve_cost(m: int, n: int, p, q, rho: float, kind: int, C=None, xs=None, xt=
                                _ptr(mu0), _ptr(nu0), ctypes.byref(r), _stream(stream))
     _check(rc)
     return X, r.as_dict(), mu, nu
+
+
+def padded(t, mult: int = 4):
+    """A 2-D tensor with the same values whose leading dimension is a multiple
+    of `mult` (a view into a wider buffer); keeps 16-byte rows aligned."""
+    import torch
+    m, n = t.shape
+    ld = -(-n // mult) * mult
+    if ld == n and t.is_contiguous():
+        return t
+    buf = torch.zeros((m, ld), dtype=t.dtype, device=t.device)
+    buf[:, :n] = t
+    return buf[:, :n]
+
+
+def solve_batched(problems, max_iter: int = 100000, tol_mode: int = TOL_RELATIVE,
+                  check_every: int = 0, flags: int = 0, tile_rows: int = 0, tile_chunks: int = 0,
+                  cache_mode: int = CACHE_AUTO, ctx: Context | None = None, stream=None):
+    """Solve a list of problems together.  Each item is a dict with C (m x n
+    tensor), p, q, rho, tol and optionally mu0, nu0 (float64 warm start); X,
+    mu and nu are allocated here (X with a 16-byte-aligned leading dimension).
+    Returns (status, [(X, result, mu, nu), ...])."""
+    import torch
+    if not problems:
+        raise ValueError("no problems")
+    C0 = problems[0]["C"]
+    ctx = ctx or default_context(C0.device.index or 0)
+    arr = (Problem * len(problems))()
+    outs = (Result * len(problems))()
+    keep = []
+    for k, pr in enumerate(problems):
+        C = pr["C"]
+        m, n = C.shape
+        if C.dtype != C0.dtype:
+            raise TypeError("all problems of a batch share one dtype")
+        X = torch.empty((m, -(-n // 4) * 4), dtype=C.dtype, device=C.device)[:, :n]
+        mu = torch.empty(m, dtype=torch.float64, device=C.device)
+        nu = torch.empty(n, dtype=torch.float64, device=C.device)
+        mu0, nu0 = pr.get("mu0"), pr.get("nu0")
+        arr[k] = Problem(m, n, C.data_ptr(), _ld(C), pr["p"].data_ptr(), pr["q"].data_ptr(),
+                         X.data_ptr(), _ld(X), float(pr["rho"]), float(pr["tol"]),
+                         mu.data_ptr(), nu.data_ptr(),
+                         None if mu0 is None else mu0.data_ptr(),
+                         None if nu0 is None else nu0.data_ptr())
+        keep.append((X, mu, nu))
+    prm = make_params(1.0, 0.0, max_iter, tol_mode, X0_PQ, check_every, flags, tile_rows,
+                      tile_chunks, 0, cache_mode)
+    rc = lib().drot_solve_batched(ctx.handle, len(problems), _dtype_code(C0), arr,
+                                  ctypes.byref(prm), outs, _stream(stream))
+    _check(rc)
+    return rc, [(X, outs[k].as_dict(), mu, nu) for k, (X, mu, nu) in enumerate(keep)]
+
+
+class MLP:
+    """The warm-start network of include/drot.h (drot_mlp_*): marshalling only."""
+
+    def __init__(self, in_dim: int, hidden: int, out_dim: int, max_batch: int, seed: int = 0,
+                 device: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().drot_mlp_create(ctypes.byref(h), device, in_dim, hidden, out_dim, max_batch,
+                                     seed), allow=(OK,))
+        self.handle = h
+        self.dims = (in_dim, hidden, out_dim)
+        k = ctypes.c_int64()
+        _check(lib().drot_mlp_num_params(h, ctypes.byref(k)), allow=(OK,))
+        self.n_params = k.value
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().drot_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_weights(self):
+        import numpy as np
+        w = np.empty(self.n_params, dtype=np.float32)
+        _check(lib().drot_mlp_get_weights(self.handle, w.ctypes.data_as(
+            ctypes.POINTER(ctypes.c_float))), allow=(OK,))
+        return w
+
+    def set_weights(self, w):
+        import numpy as np
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        _check(lib().drot_mlp_set_weights(self.handle, w.ctypes.data_as(
+            ctypes.POINTER(ctypes.c_float))), allow=(OK,))
+
+    def forward(self, x, stream=None):
+        import torch
+        y = torch.empty((x.shape[0], self.dims[2]), dtype=torch.float32, device=x.device)
+        _check(lib().drot_mlp_forward(self.handle, x.shape[0], _ptr(x), _ptr(y), _stream(stream)),
+               allow=(OK,))
+        return y
+
+    def gradients(self, x, t, stream=None):
+        import torch
+        g = torch.empty(self.n_params, dtype=torch.float32, device=x.device)
+        loss = ctypes.c_double()
+        _check(lib().drot_mlp_gradients(self.handle, x.shape[0], _ptr(x), _ptr(t), _ptr(g),
+                                        ctypes.byref(loss), _stream(stream)), allow=(OK,))
+        return loss.value, g
+
+    def train_step(self, x, t, lr: float, stream=None) -> float:
+        loss = ctypes.c_double()
+        _check(lib().drot_mlp_train_step(self.handle, x.shape[0], _ptr(x), _ptr(t),
+                                         ctypes.c_float(lr), ctypes.byref(loss),
+                                         _stream(stream)), allow=(OK,))
+        return loss.value
 
 
 @dataclass

@@ -1,0 +1,187 @@
+"""Learned warm start for DROT on grid histograms (not part of the paper).
+
+A network maps the marginals (p, q) of a problem on a 32 x 32 grid to initial
+dual variables (mu, nu); DROT then starts from phi_0 = rho mu, psi_0 = rho nu
+(valid from any start by Lemma 1), and cold DROT remains the fallback and the
+judge of the final error.  Everything numerical runs on the GPU through
+libdrot.so: the training targets come from DROT itself (batched solver), and
+the network is trained and evaluated with the library's MLP kernels.
+
+    python -m paper_2110_11738_amd.warmstart --train 4096 --test 512
+
+Targets are gauge-fixed: (mu, nu) and (mu + t, nu - t) describe the same
+duals, so the pair with mean(mu) = 0 is learned.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from gen import grid_cost, grid_histogram_pair  # noqa: E402
+
+from . import drot  # noqa: E402
+
+SIDE = 32
+N = SIDE * SIDE
+
+
+def log(msg):
+    print(f"[warmstart] {msg}", file=sys.stderr, flush=True)
+
+
+def rho_grid() -> float:
+    return (1.0 / math.log(N)) / (2 * N)
+
+
+def features(ps: np.ndarray, qs: np.ndarray) -> np.ndarray:
+    """Network input: the two histograms scaled by the grid size (mean 1)."""
+    return np.concatenate([ps * N, qs * N], axis=1).astype(np.float32)
+
+
+def gauge_fix(mu: np.ndarray, nu: np.ndarray) -> np.ndarray:
+    t = mu.mean(axis=1, keepdims=True)
+    return np.concatenate([mu - t, nu + t], axis=1).astype(np.float32)
+
+
+def make_pairs(count: int, split: int, start: int = 0):
+    ps = np.empty((count, N))
+    qs = np.empty((count, N))
+    for k in range(count):
+        ps[k], qs[k] = grid_histogram_pair(start + k, split, SIDE)
+    return ps, qs
+
+
+def solve_pairs(ctx, C, ps, qs, tol=1e-4, max_iter=500_000, mu0=None, nu0=None, chunk=512):
+    """Solve every pair with the batched GPU solver (shared cost matrix).
+    Returns mu, nu (float64, per pair), iterations, device seconds, objectives."""
+    import torch
+    dev = C.device
+    out_mu, out_nu, iters, secs, objs, status = [], [], [], [], [], []
+    rho = rho_grid()
+    for s in range(0, len(ps), chunk):
+        probs = []
+        for k in range(s, min(s + chunk, len(ps))):
+            pr = {"C": C, "p": torch.tensor(ps[k], dtype=torch.float32, device=dev),
+                  "q": torch.tensor(qs[k], dtype=torch.float32, device=dev),
+                  "rho": rho, "tol": tol}
+            if mu0 is not None:
+                pr["mu0"] = torch.tensor(mu0[k], dtype=torch.float64, device=dev)
+                pr["nu0"] = torch.tensor(nu0[k], dtype=torch.float64, device=dev)
+            probs.append(pr)
+        rc, outs = drot.solve_batched(probs, max_iter=max_iter, check_every=64, ctx=ctx)
+        for X, r, mu, nu in outs:
+            out_mu.append(mu.cpu().numpy())
+            out_nu.append(nu.cpu().numpy())
+            iters.append(r["iters"])
+            secs.append(r["seconds_to_tol"])
+            objs.append(r["objective"])
+            status.append(r["status"])
+        log(f"solved {min(s + chunk, len(ps))}/{len(ps)} (mean iterations {np.mean(iters):.0f})")
+    return (np.array(out_mu), np.array(out_nu), np.array(iters), np.array(secs), np.array(objs),
+            np.array(status))
+
+
+def train(net, X, T, epochs: int, batch: int, lr: float, seed: int = 0):
+    """Adam over shuffled mini-batches (the last partial batch is dropped)."""
+    import torch
+    rng = np.random.default_rng(seed)
+    Xd = torch.tensor(X, device="cuda")
+    Td = torch.tensor(T, device="cuda")
+    losses = []
+    for ep in range(epochs):
+        order = torch.tensor(rng.permutation(len(X)), device="cuda")
+        tot = 0.0
+        nb = len(X) // batch
+        for b in range(nb):
+            idx = order[b * batch:(b + 1) * batch]
+            tot += net.train_step(Xd[idx].contiguous(), Td[idx].contiguous(), lr)
+        losses.append(tot / max(nb, 1))
+    return losses
+
+
+def predict(net, X, batch: int):
+    """Network outputs for every row of X (padding the last batch)."""
+    import torch
+    out = []
+    for s in range(0, len(X), batch):
+        xb = np.zeros((batch, X.shape[1]), dtype=np.float32)
+        part = X[s:s + batch]
+        xb[:len(part)] = part
+        y = net.forward(torch.tensor(xb, device="cuda")).cpu().numpy()
+        out.append(y[:len(part)])
+    Y = np.concatenate(out).astype(np.float64)
+    return Y[:, :N], Y[:, N:]
+
+
+def run(n_train: int, n_test: int, epochs: int, batch: int, lr: float, tol: float,
+        hidden: int = 512, seed: int = 0) -> dict:
+    import torch
+    ctx = drot.Context(0)
+    C = torch.tensor(grid_cost(SIDE), dtype=torch.float32, device="cuda")
+    t0 = time.time()
+    ps, qs = make_pairs(n_train, 0)
+    pt, qt = make_pairs(n_test, 1)
+    log(f"generated {n_train} + {n_test} pairs in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    mu, nu, it_train, _, _, st_train = solve_pairs(ctx, C, ps, qs, tol)
+    t_data = time.time() - t0
+    X = features(ps, qs)
+    T = gauge_fix(mu, nu)
+    net = drot.MLP(2 * N, hidden, 2 * N, max_batch=max(batch, 64), seed=seed)
+    t0 = time.time()
+    losses = train(net, X, T, epochs, batch, lr, seed)
+    t_train = time.time() - t0
+    log(f"trained {epochs} epochs in {t_train:.1f}s, loss {losses[0]:.4e} -> {losses[-1]:.4e}")
+    # held-out: cold vs warm (the warm solve falls back to cold if it fails)
+    mu_c, nu_c, it_c, s_c, obj_c, st_c = solve_pairs(ctx, C, pt, qt, tol)
+    mu_hat, nu_hat = predict(net, features(pt, qt), max(batch, 64))
+    mu_w, nu_w, it_w, s_w, obj_w, st_w = solve_pairs(ctx, C, pt, qt, tol, mu0=mu_hat, nu0=nu_hat)
+    fallback = st_w != 0
+    it_w_eff = np.where(fallback, it_w + it_c, it_w)
+    rel_obj = np.abs(obj_w - obj_c) / np.abs(obj_c)
+    Tt = gauge_fix(mu_c, nu_c)
+    pred_err = float(np.sqrt(((np.concatenate([mu_hat, nu_hat], 1) - Tt) ** 2).mean()))
+    report = {
+        "train_pairs": n_train, "test_pairs": n_test, "epochs": epochs, "batch": batch, "lr": lr,
+        "tol": tol, "hidden": hidden, "seconds_data": t_data, "seconds_train": t_train,
+        "train_iters_mean": float(it_train.mean()), "train_unconverged": int((st_train != 0).sum()),
+        "loss_first": losses[0], "loss_last": losses[-1],
+        "test_rmse_duals": pred_err,
+        "cold_iters_mean": float(it_c.mean()), "cold_iters_median": float(np.median(it_c)),
+        "warm_iters_mean": float(it_w_eff.mean()), "warm_iters_median": float(np.median(it_w_eff)),
+        "cold_seconds_mean": float(s_c.mean()), "warm_seconds_mean": float(s_w.mean()),
+        "warm_fallbacks": int(fallback.sum()),
+        "objective_rel_diff_warm_vs_cold_max": float(rel_obj.max()),
+        "iteration_ratio_mean": float(it_w_eff.mean() / it_c.mean()),
+    }
+    net.close()
+    ctx.close()
+    return report
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=4096)
+    ap.add_argument("--test", type=int, default=512)
+    ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--tol", type=float, default=1e-4)
+    ap.add_argument("--hidden", type=int, default=512)
+    args = ap.parse_args()
+    rep = run(args.train, args.test, args.epochs, args.batch, args.lr, args.tol, args.hidden)
+    print(json.dumps(rep), flush=True)
+
+
+if __name__ == "__main__":
+    main()

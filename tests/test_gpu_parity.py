@@ -431,3 +431,55 @@ def test_ragged_width_on_the_vector_path(ctx, dtype):
     assert _rel_max(X.double().cpu().numpy(), R.X) <= TOL[dtype][0]
     assert torch.all(Xbig[:, 203] == -2.0)
     assert abs(res["objective"] - R.info["pobj"]) <= TOL[dtype][2] * R.info["pobj"]
+
+
+# ---------------------------------------------------------------------------
+# Batched ragged problems
+# ---------------------------------------------------------------------------
+def _batch_inputs(insts):
+    torch = _torch()
+    from paper_2110_11738_amd import drot
+    probs = []
+    for I in insts:
+        probs.append({"C": drot.padded(torch.tensor(I.C, dtype=torch.float32, device="cuda")),
+                      "p": torch.tensor(I.p, dtype=torch.float32, device="cuda"),
+                      "q": torch.tensor(I.q, dtype=torch.float32, device="cuda"),
+                      "rho": I.rho, "tol": I.tol})
+    return probs
+
+
+def test_batched_trajectories_match_oracle(ctx):
+    """A ragged batch (widths not multiples of 4, a 1-row problem, a tiny
+    one) advanced together: every problem's X_K and duals match the oracle."""
+    from gen import config_batch
+    from paper_2110_11738_amd import drot
+    insts = [round_to(I, np.float32) for I in config_batch(9, 40, 300, seed=1)]
+    insts.append(round_to(config_mixture_2d(18, 1, 37), np.float32))
+    insts.append(round_to(config_mixture_2d(19, 5, 3), np.float32))
+    K = 30
+    rc, outs = drot.solve_batched(_batch_inputs(insts), max_iter=K, check_every=8, ctx=ctx)
+    for I, (X, res, mu, nu) in zip(insts, outs):
+        R = ref.solve(I.C, I.p, I.q, I.rho, 0.0, max_iter=K)
+        ex = _rel_max(X.double().cpu().numpy(), R.X)
+        print(f"[batch] {I.name}: iters {res['iters']} X {ex:.2e}", flush=True)
+        assert res["iters"] == K
+        assert ex <= TOL["float32"][0]
+        assert _rel_max(mu.cpu().numpy(), R.mu) <= TOL["float32"][1]
+
+
+def test_batched_per_problem_stop(ctx):
+    """Each problem stops on its own test; results match single solves."""
+    from gen import config_batch
+    from paper_2110_11738_amd import drot
+    insts = [round_to(I, np.float32) for I in config_batch(6, 64, 200, seed=2)]
+    rc, outs = drot.solve_batched(_batch_inputs(insts), max_iter=2_000_000, check_every=16,
+                                  ctx=ctx)
+    assert rc == drot.OK
+    iters = set()
+    for I, (X, res, mu, nu) in zip(insts, outs):
+        Xs, rs, mus, nus = _run(ctx, I, "float32", 2_000_000, tol=I.tol)
+        print(f"[batch-stop] {I.name}: {res['iters']} vs single {rs['iters']}", flush=True)
+        assert res["status"] == 0 and res["eps_primal"] <= I.tol
+        assert abs(res["objective"] - rs["objective"]) <= 1e-4 * rs["objective"]
+        iters.add(res["iters"])
+    assert len(iters) > 1

@@ -273,3 +273,34 @@ def test_paper_protocol_assignment_accuracy():
     R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 1e-4, max_iter=100_000)
     assert R.status == 0
     assert abs(R.info["pobj"] - opt) / opt < 1e-3
+
+
+# --------------------------------------------------------------------------
+# Warm-start MLP reference (not from the paper): pinned by finite differences
+# --------------------------------------------------------------------------
+def test_mlp_reference_gradient_matches_finite_differences():
+    from oracle import mlp_ref
+    rng = np.random.default_rng(5)
+    dims = (6, 5, 4)
+    n_par = 5 * 6 + 5 + 5 * 5 + 5 + 4 * 5 + 4
+    theta = rng.standard_normal(n_par) * 0.5
+    x = rng.standard_normal((7, 6))
+    t = rng.standard_normal((7, 4))
+    loss, g = mlp_ref.loss_and_grad(theta, x, t, dims, bf16=False)
+    h = 1e-6
+    fd = np.empty(n_par)
+    for k in range(n_par):
+        e = np.zeros(n_par)
+        e[k] = h
+        fd[k] = (mlp_ref.loss_and_grad(theta + e, x, t, dims, bf16=False)[0]
+                 - mlp_ref.loss_and_grad(theta - e, x, t, dims, bf16=False)[0]) / (2 * h)
+    np.testing.assert_allclose(g, fd, rtol=1e-6, atol=1e-8)
+    assert abs(loss - ((mlp_ref.forward(theta, x, dims, bf16=False) - t) ** 2).mean()) < 1e-15
+
+
+def test_bf16_rounding_reference():
+    from oracle import mlp_ref
+    # exactly representable values stay; ties go to even; 1 + 2^-8 rounds down
+    vals = np.array([1.0, 1.0 + 2.0 ** -7, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -2.5, 0.0])
+    out = mlp_ref.bf16_round(vals)
+    np.testing.assert_array_equal(out, [1.0, 1.0 + 2.0 ** -7, 1.0, 1.0 + 2.0 ** -6, -2.5, 0.0])
