@@ -84,7 +84,9 @@ typedef enum { DROT_CACHE_AUTO = 0, DROT_CACHE_CACHED = 1, DROT_CACHE_STREAM = 2
 
 /* drot_params.flags */
 #define DROT_FLAG_NO_GRAPH 0x1    /* launch eagerly instead of replaying hipGraphs */
-#define DROT_FLAG_TIME_SWEEP 0x2  /* bracket sweep launches with hipEvents (see drot_result) */
+/* Time sweep launches with hipEvents (see drot_result): in graph mode the two
+ * sweeps in the middle of every graph replay, in eager mode every sweep. */
+#define DROT_FLAG_TIME_SWEEP 0x2
 /* The skip-C schedule of the paper's Claim 1 (Section 3, "Main kernel"):
  * iterations alternate between one that reads X and C and stores
  * W = X_{k+1} - rho C, and one that reads only W and stores

@@ -257,7 +257,8 @@ def test_timed_sweeps_change_nothing(ctx, flags):
     timed = _run(ctx, inst, "float32", 80, check_every=16, flags=fl)
     np.testing.assert_array_equal(base[0], timed[0])
     np.testing.assert_array_equal(base[2], timed[2])
-    assert timed[1]["sweep_timed"] == 80
+    # eager: every sweep; graphs of 16: two sweeps per replay (5 replays)
+    assert timed[1]["sweep_timed"] == (80 if flags == "eager" else 10)
     assert timed[1]["sweep_ms_total"] > 0
 
 
@@ -436,7 +437,7 @@ def test_ragged_width_on_the_vector_path(ctx, dtype):
 # ---------------------------------------------------------------------------
 # Batched ragged problems
 # ---------------------------------------------------------------------------
-def _batch_inputs(insts):
+def _batch_inputs(insts, tol=None):
     torch = _torch()
     from paper_2110_11738_amd import drot
     probs = []
@@ -444,7 +445,7 @@ def _batch_inputs(insts):
         probs.append({"C": drot.padded(torch.tensor(I.C, dtype=torch.float32, device="cuda")),
                       "p": torch.tensor(I.p, dtype=torch.float32, device="cuda"),
                       "q": torch.tensor(I.q, dtype=torch.float32, device="cuda"),
-                      "rho": I.rho, "tol": I.tol})
+                      "rho": I.rho, "tol": I.tol if tol is None else tol})
     return probs
 
 
@@ -457,7 +458,8 @@ def test_batched_trajectories_match_oracle(ctx):
     insts.append(round_to(config_mixture_2d(18, 1, 37), np.float32))
     insts.append(round_to(config_mixture_2d(19, 5, 3), np.float32))
     K = 30
-    rc, outs = drot.solve_batched(_batch_inputs(insts), max_iter=K, check_every=8, ctx=ctx)
+    rc, outs = drot.solve_batched(_batch_inputs(insts, tol=0.0), max_iter=K, check_every=8,
+                                  ctx=ctx)
     for I, (X, res, mu, nu) in zip(insts, outs):
         R = ref.solve(I.C, I.p, I.q, I.rho, 0.0, max_iter=K)
         ex = _rel_max(X.double().cpu().numpy(), R.X)
