@@ -8,10 +8,11 @@ m x n plan plus the O(m+n) dual update and the stopping test.  The timed
 workload is the 4096 x 4096 float32 problem (2-D five-Gaussian point clouds,
 squared-Euclidean cost normalised to max 1, Dirichlet(1) marginals,
 rho = (1/ln m)/(m+n)), resident in HBM before timing starts.  One JSON line
-is printed with iterations/s (`value`), the roofline of the sweep kernel
-(timed with hipEvents around every sweep launch of the timed region), the
-time to the 1e-4 relative stopping test, the 20000 x 20000 roofline instance
-and the CPU oracle timed on a bounded sample.
+is printed with iterations/s (`value`, graph replays without events), the
+roofline of the sweep kernel (a second timed region of the same length with
+eager launches, every sweep carrying hipExtLaunchKernel start/stop events),
+the time to the 1e-4 relative stopping test, the 20000 x 20000 roofline
+instance and the CPU oracle timed on a bounded sample.
 """
 import argparse
 import json
@@ -54,31 +55,16 @@ def upload(inst):
     return C, p, q
 
 
-def timed_iterations(ctx, C, p, q, rho, steps, warmup, args, timed_events=True):
-    """Bind, warm up, then time exactly `steps` iterations.  Returns
-    (seconds, sweep_ms_avg or None, sweep_count, result)."""
-    from paper_2110_11738_amd import drot
-    return timed_iterations_flags(ctx, C, p, q, rho, steps, warmup, args,
-                                  drot.FLAG_TIME_SWEEP if timed_events else 0)
-
-
-def timed_iterations_flags(ctx, C, p, q, rho, steps, warmup, args, flags):
+def timed_run(ctx, bind, steps, warmup, flags):
+    """Bind with `flags` (bind(flags, max_iter)), run `warmup` iterations,
+    then time exactly `steps`.  Returns (seconds, average sweep ms or None,
+    sweeps timed)."""
     import torch
-    from paper_2110_11738_amd import drot
-    m, n = C.shape
-    X = torch.empty((m, n), dtype=C.dtype, device=C.device)
-    if flags & drot.FLAG_SKIP_C:
-        flags |= drot.FLAG_TIME_SWEEP
-    prm = drot.make_params(rho, 0.0, warmup + steps + 1, check_every=args.check_every,
-                           flags=flags, tile_rows=args.tile_rows, tile_chunks=args.tile_chunks,
-                           tile_unroll=args.tile_unroll, cache_mode=args.cache_mode,
-                           tile_groups=args.tile_groups)
-    ctx.bind(C, p, q, X, prm)
+    bind(flags, warmup + steps + 1)
     if warmup:
         ctx.iterate(warmup)
     torch.cuda.synchronize()
-    before = ctx.finish()  # cheap final pass, resets nothing; gives sweep counters so far
-    ms0, n0 = before["sweep_ms_total"], before["sweep_timed"]
+    before = ctx.finish()  # read-only final pass: sweep counters so far
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.iterate(steps)
@@ -86,30 +72,46 @@ def timed_iterations_flags(ctx, C, p, q, rho, steps, warmup, args, flags):
     t1 = time.perf_counter()
     res = ctx.finish()
     assert res["iters"] == warmup + steps, res
-    cnt = res["sweep_timed"] - n0
-    avg = (res["sweep_ms_total"] - ms0) / cnt if cnt > 0 else None
-    return t1 - t0, avg, cnt, res
+    cnt = res["sweep_timed"] - before["sweep_timed"]
+    avg = (res["sweep_ms_total"] - before["sweep_ms_total"]) / cnt if cnt > 0 else None
+    return t1 - t0, avg, cnt
 
 
-def timed_cost_iterations(ctx, m, n, cost, p, q, rho, steps, warmup, keep):
-    """Like timed_iterations for a cost descriptor (bfloat16 / coordinates)."""
+def measure(ctx, bind, steps, warmup, flags=0):
+    """Two timed regions of the same workload: graph replays without events
+    (the throughput), then eager launches in which every sweep carries
+    hipExtLaunchKernel start/stop events (the sweep kernel's own average
+    duration, the figure the roofline uses)."""
+    from paper_2110_11738_amd import drot
+    secs, _, _ = timed_run(ctx, bind, steps, warmup, flags)
+    esecs, ms, cnt = timed_run(ctx, bind, steps, warmup,
+                               flags | drot.FLAG_NO_GRAPH | drot.FLAG_TIME_SWEEP)
+    return {"seconds": secs, "seconds_eager": esecs, "sweep_ms": ms, "sweeps_timed": cnt}
+
+
+def dense_binder(ctx, C, p, q, rho, args):
+    import torch
+    from paper_2110_11738_amd import drot
+    X = torch.empty(C.shape, dtype=C.dtype, device=C.device)
+
+    def bind(flags, max_iter):
+        prm = drot.make_params(rho, 0.0, max_iter, check_every=args.check_every, flags=flags,
+                               tile_rows=args.tile_rows, tile_chunks=args.tile_chunks,
+                               tile_unroll=args.tile_unroll, cache_mode=args.cache_mode,
+                               tile_groups=args.tile_groups)
+        ctx.bind(C, p, q, X, prm)
+    return bind
+
+
+def cost_binder(ctx, m, n, cost, p, q, rho, keep):
     import torch
     from paper_2110_11738_amd import drot
     X = torch.empty((m, n), dtype=torch.float32, device="cuda")
-    prm = drot.make_params(rho, 0.0, warmup + steps + 1, check_every=64,
-                           flags=drot.FLAG_TIME_SWEEP)
-    ctx.bind_cost(m, n, cost, p, q, X, prm, keep=keep)
-    ctx.iterate(warmup)
-    torch.cuda.synchronize()
-    before = ctx.finish()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.iterate(steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    res = ctx.finish()
-    cnt = res["sweep_timed"] - before["sweep_timed"]
-    return t1 - t0, (res["sweep_ms_total"] - before["sweep_ms_total"]) / cnt
+
+    def bind(flags, max_iter):
+        prm = drot.make_params(rho, 0.0, max_iter, check_every=64, flags=flags)
+        ctx.bind_cost(m, n, cost, p, q, X, prm, keep=keep)
+    return bind
 
 
 def precision_section(ctx, steps=200, warmup=20):
@@ -139,7 +141,8 @@ def precision_section(ctx, steps=200, warmup=20):
                                   ("coords", drot.COST_COORDS, (xs, xt), 8)):
         cost = drot.make_cost(kind, C=C32 if kind == drot.COST_DENSE else Cb, xs=xs, xt=xt,
                               scale=scale)
-        secs, sw = timed_cost_iterations(ctx, m, n, cost, p, q, rho, steps, warmup, keep)
+        r = measure(ctx, cost_binder(ctx, m, n, cost, p, q, rho, keep), steps, warmup)
+        secs, sw = r["seconds"], r["sweep_ms"]
         ach = bpe * m * n / (sw * 1e-3) / 1e9
         out[name] = {"iter_per_s": steps / secs, "sweep_us": sw * 1e3, "bytes_per_entry": bpe,
                      "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS}
@@ -201,7 +204,7 @@ def cpu_baseline(inst, budget_s=20.0):
     ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=1)
     t_one = time.perf_counter() - t0
     k = max(2, int(budget_s / max(t_one / 2, 1e-3)))
-    k = min(k, 200)
+    k = min(k, 1000)
     t0 = time.perf_counter()
     ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=1 + k)
     t_k = time.perf_counter() - t0
@@ -268,18 +271,21 @@ def main():
     C, p, q = upload(inst)
     m, n = args.m, args.n
     log(f"timing {args.steps} iterations after {args.warmup} warm-up iterations")
-    secs, sweep_ms, cnt, res = timed_iterations(ctx, C, p, q, inst.rho, args.steps, args.warmup, args)
+    bind = dense_binder(ctx, C, p, q, inst.rho, args)
+    r = measure(ctx, bind, args.steps, args.warmup)
+    secs, sweep_ms, cnt = r["seconds"], r["sweep_ms"], r["sweeps_timed"]
     value = args.steps / secs
-    secs_ne, _, _, _ = timed_iterations(ctx, C, p, q, inst.rho, args.steps, args.warmup, args,
-                                        timed_events=False)
     alg_bytes = BYTES_PER_ENTRY_F32 * m * n
-    achieved = alg_bytes / (sweep_ms * 1e-3) / 1e9 if sweep_ms else None
+    achieved = alg_bytes / (sweep_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
             "kernel": "sweep_kernel<float,iter>", "bytes_per_launch": alg_bytes,
-            "avg_launch_us": sweep_ms * 1e3 if sweep_ms else None, "launches_timed": cnt}
+            "avg_launch_us": sweep_ms * 1e3, "launches_timed": cnt,
+            "timing": "hipExtLaunchKernel start/stop events on every sweep of a second timed "
+                      "region (eager launches, same workload and length)",
+            "eager_iter_per_s": args.steps / r["seconds_eager"]}
     log(f"{value:.1f} it/s ({1e3 * secs / args.steps:.4f} ms/it); sweep {sweep_ms * 1e3:.2f} us "
-        f"-> {achieved:.0f} GB/s; without events {args.steps / secs_ne:.1f} it/s")
+        f"-> {achieved:.0f} GB/s; eager {args.steps / r['seconds_eager']:.1f} it/s")
 
     out = {
         "metric": "DROT iters/s + time-to-1e-4 residual at 4096^2 and 20000^2; HBM GB/s vs peak",
@@ -294,19 +300,13 @@ def main():
                    "tile_unroll": args.tile_unroll, "cache_mode": args.cache_mode,
                    "tile_groups": args.tile_groups,
                    "check_every": args.check_every, "parallelism": "single GPU"},
-        "value_without_sweep_events": args.steps / secs_ne,
         "roofline": roof,
     }
 
     # ---- the paper's skip-C schedule on the same workload ---------------------
     if not args.no_skipc:
-        class _A:
-            pass
-        sk = _A()
-        for k, v in vars(args).items():
-            setattr(sk, k, v)
-        secs_s, sweep_s, _, _ = timed_iterations_flags(ctx, C, p, q, inst.rho, args.steps,
-                                                       args.warmup, sk, drot.FLAG_SKIP_C)
+        r = measure(ctx, bind, args.steps, args.warmup, drot.FLAG_SKIP_C)
+        secs_s, sweep_s = r["seconds"], r["sweep_ms"]
         out["skip_c"] = {"iter_per_s": args.steps / secs_s, "avg_sweep_us": sweep_s * 1e3,
                          "bytes_per_entry_avg": 10,
                          "achieved_GBs": 10 * m * n / (sweep_s * 1e-3) / 1e9}
@@ -350,7 +350,8 @@ def main():
         rho_l = linst.rho
         del linst
         ksteps, kwarm = 40, 5
-        secs_l, sweep_l, cnt_l, _ = timed_iterations(ctx, C, p, q, rho_l, ksteps, kwarm, args)
+        r = measure(ctx, dense_binder(ctx, C, p, q, rho_l, args), ksteps, kwarm)
+        secs_l, sweep_l, cnt_l = r["seconds"], r["sweep_ms"], r["sweeps_timed"]
         ab = BYTES_PER_ENTRY_F32 * L * L
         ach = ab / (sweep_l * 1e-3) / 1e9
         out["large"] = {"m": L, "n": L, "iter_per_s": ksteps / secs_l,

@@ -84,8 +84,12 @@ typedef enum { DROT_CACHE_AUTO = 0, DROT_CACHE_CACHED = 1, DROT_CACHE_STREAM = 2
 
 /* drot_params.flags */
 #define DROT_FLAG_NO_GRAPH 0x1    /* launch eagerly instead of replaying hipGraphs */
-/* Time sweep launches with hipEvents (see drot_result): in graph mode the two
- * sweeps in the middle of every graph replay, in eager mode every sweep. */
+/* Time sweep launches with hipEvents (see drot_result).  Eager mode
+ * (DROT_FLAG_NO_GRAPH): every sweep goes through hipExtLaunchKernel, whose
+ * events carry the dispatch's own start and end times, so the reading is the
+ * kernel's duration.  Graph mode: event-record nodes around the two sweeps in
+ * the middle of every graph replay; that reading also holds the dispatch
+ * latency after the start event, a few microseconds per sweep. */
 #define DROT_FLAG_TIME_SWEEP 0x2
 /* The skip-C schedule of the paper's Claim 1 (Section 3, "Main kernel"):
  * iterations alternate between one that reads X and C and stores

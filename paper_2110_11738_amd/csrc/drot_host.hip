@@ -268,10 +268,10 @@ int iter_mode(const drot_ctx* c, int64_t idx) {
   return (idx & 1) ? kIterB : kIterA;
 }
 
+// One iteration: sweep + aux.  With events (eager timing) the sweep's start
+// and end are the dispatch's own timestamps.
 int launch_iteration(drot_ctx* c, hipStream_t s, hipEvent_t e0, hipEvent_t e1, int mode) {
-  if (e0) HIP_TRY(hipEventRecord(e0, s));
-  HIP_TRY(launch_sweep(c->dtype, mode, c->geo.tile, c->sa, s));
-  if (e1) HIP_TRY(hipEventRecord(e1, s));
+  HIP_TRY(launch_sweep(c->dtype, mode, c->geo.tile, c->sa, s, e0, e1));
   HIP_TRY(launch_aux(c->dtype, mode, c->sa, s));
   return DROT_OK;
 }
@@ -334,7 +334,7 @@ int build_timed_graph(drot_ctx* c, int G, hipGraph_t* out) {
     const int q = k % kinds;
     const bool timed = k >= t0 && k < t0 + tn;
     const int slot = k - t0;
-    hipGraphNode_t e0 = nullptr, s, e1 = nullptr, x;
+    hipGraphNode_t e0 = nullptr, s = nullptr, e1 = nullptr, x = nullptr;
     const hipGraphNode_t* dep = prev ? &prev : nullptr;
     size_t ndep = prev ? 1 : 0;
     if (timed) {

@@ -14,11 +14,13 @@ constexpr int kTileSlots = 2;      // per-tile scalar partials (see TileSlot)
 constexpr int kSlots = 13;         // per-finisher scalar partials (see Slot)
 constexpr int kTraceCap = 65536;   // per-iteration records kept on the device
 constexpr int kTraceWidth = 8;
-constexpr int kAuxCols = 32;       // columns per aux workgroup
+constexpr int kAuxCols = 32;       // columns per aux column workgroup
+constexpr int kAuxRows = kWave;    // rows per aux row workgroup
 
-// Workgroups of one aux launch: column groups of kAuxCols, then rows by kBlock.
+// Workgroups of one aux launch: column groups of kAuxCols, then row groups of
+// kAuxRows.
 __host__ __device__ inline int64_t aux_workgroups(int64_t m, int64_t n) {
-  return (n + kAuxCols - 1) / kAuxCols + (m + kBlock - 1) / kBlock;
+  return (n + kAuxCols - 1) / kAuxCols + (m + kAuxRows - 1) / kAuxRows;
 }
 
 // What one sweep + aux pair does.
@@ -125,7 +127,7 @@ struct SweepArgs {
   void* colpart;           // [n_rg][ldcp] (float in the FP32 iteration, else double)
   void* rowpart;           // [n_ct][m]
   double* tiles;           // [n_rg * n_ct][kTileSlots], workgroup (g, ct) at g * n_ct + ct
-  double* blockpart;       // [aux workgroups][kSlots]
+  double* blockpart;       // [kSlots][aux workgroups] (slot-major)
   double* trace;           // [trace_cap][kTraceWidth]
   int64_t trace_cap;       // records kept (ring)
   double wall_rate;        // wall_clock64 ticks per second
@@ -144,8 +146,10 @@ struct TileCfg {
 };
 
 // Launchers (drot_kernels.hip).
+// With e0 / e1 given, the sweep goes through hipExtLaunchKernel, which
+// records the dispatch's own start and end times in those events.
 hipError_t launch_sweep(int dtype, int mode, const TileCfg& t, const SweepArgs& a,
-                        hipStream_t s);
+                        hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_aux(int dtype, int mode, const SweepArgs& a, hipStream_t s);
 hipError_t launch_prep(const SweepArgs& a, hipStream_t s);
 hipError_t launch_maxc(const SweepArgs& a, hipStream_t s);

@@ -36,6 +36,7 @@
 // boundary between sweep and aux is the device-wide release/acquire point: a
 // device-scope fence inside the sweep would write back the L2 (full of the
 // freshly written plan) once per workgroup.
+#include <hip/hip_ext.h>
 #include <type_traits>
 
 #include "drot_internal.h"
@@ -87,6 +88,26 @@ __device__ __forceinline__ V wave_sum(V v) {
   return lane63(v);
 }
 
+// wave_sum of N values at once: each DPP step is applied to all N before the
+// next, so that the N dependency chains overlap.  Every lane gets the totals.
+template <int N>
+__device__ __forceinline__ void wave_sum_n(double (&v)[N]) {
+#pragma unroll
+  for (int s = 0; s < N; ++s) v[s] += dpp<0xB1>(v[s]);
+#pragma unroll
+  for (int s = 0; s < N; ++s) v[s] += dpp<0x4E>(v[s]);
+#pragma unroll
+  for (int s = 0; s < N; ++s) v[s] += dpp<0x141>(v[s]);
+#pragma unroll
+  for (int s = 0; s < N; ++s) v[s] += dpp<0x140>(v[s]);
+#pragma unroll
+  for (int s = 0; s < N; ++s) v[s] += dpp<0x142, 0xA>(v[s]);
+#pragma unroll
+  for (int s = 0; s < N; ++s) v[s] += dpp<0x143, 0xC>(v[s]);
+#pragma unroll
+  for (int s = 0; s < N; ++s) v[s] = lane63(v[s]);
+}
+
 // ---------------------------------------------------------------------------
 // Types and memory helpers.
 // ---------------------------------------------------------------------------
@@ -94,7 +115,6 @@ __device__ __forceinline__ V wave_sum(V v) {
 // else accumulates in float64.
 constexpr bool is_iter(int mode) { return mode == kIter || mode == kIterA || mode == kIterB; }
 constexpr bool is_final(int mode) { return mode == kFinal || mode == kFinalW; }
-constexpr bool is_init(int mode) { return mode == kInitPQ || mode == kInitX; }
 
 template <typename T, int MODE>
 struct PartialOf {
@@ -203,44 +223,115 @@ __device__ __forceinline__ void block_sum_slots(double (&acc)[kSlots],
   }
 }
 
-// Run by the last aux workgroup: fixed-order sum of all workgroups' scalar
-// partials, then the scalar steps of the iteration (or of the initialisation
-// or the final evaluation).
+// The state scalars that the aux kernel and its finisher read.  Every
+// workgroup loads them when it starts, so that the last workgroup's scalar
+// steps wait on no further load; nothing in them changes during the launch
+// (only the last workgroup writes the state, after all others are done).
+struct StateIn {
+  double rho, tol, alpha, sum_p, sum_q, norm_pq, norm_c;
+  double cphi, cpsi, sum_phi0, sum_psi0;
+  int64_t iter, max_iter;
+  uint64_t t_start;
+  int tol_mode, done;
+};
+
+__device__ __forceinline__ StateIn load_state(const DevState* st) {
+  StateIn v;
+  v.rho = st->rho;
+  v.tol = st->tol;
+  v.alpha = st->alpha;
+  v.sum_p = st->sum_p;
+  v.sum_q = st->sum_q;
+  v.norm_pq = st->norm_pq;
+  v.norm_c = st->norm_c;
+  v.cphi = st->cphi;
+  v.cpsi = st->cpsi;
+  v.sum_phi0 = st->sum_phi0;
+  v.sum_psi0 = st->sum_psi0;
+  v.iter = st->iter;
+  v.max_iter = st->max_iter;
+  v.t_start = st->t_start;
+  v.tol_mode = st->tol_mode;
+  v.done = st->done;
+  return v;
+}
+
+// Run by wave 0 of the last aux workgroup (all lanes active): fixed-order sum
+// of all workgroups' scalar partials, then, in lane 0, the scalar steps of the
+// iteration (or of the initialisation or the final evaluation).  `blockpart`
+// is slot-major ([kSlots][nb]); in the iteration a column workgroup fills only
+// the column and tile slots and a row workgroup the row and tile slots, and
+// the sum skips the others.
 template <int MODE>
-__device__ void finish_global(const SweepArgs& a, int nb, double (&red)[kSlots][kWaves]) {
+__device__ void finish_global(const SweepArgs& a, const StateIn& sv, int nb, int col_wgs) {
+  constexpr int B = 4;  // blockpart columns per lane in flight
+  const int lane = threadIdx.x;
   double acc[kSlots];
 #pragma unroll
   for (int s = 0; s < kSlots; ++s) acc[s] = 0.0;
-  for (int k = threadIdx.x; k < nb; k += kBlock)
+  for (int k0 = 0; k0 < nb; k0 += B * kWave) {
+    double v[B][kSlots];
 #pragma unroll
-    for (int s = 0; s < kSlots; ++s) acc[s] += load_agent(a.blockpart + (int64_t)k * kSlots + s);
-  block_sum_slots(acc, red);
-  if (threadIdx.x != 0) return;
+    for (int u = 0; u < B; ++u) {
+      const int k = k0 + u * kWave + lane;
+#pragma unroll
+      for (int s = 0; s < kSlots; ++s) {
+        bool use = k < nb;
+        if (is_iter(MODE)) {
+          if (s == kSR || s == kSR2 || s == kSPphi) use = use && k >= col_wgs;
+          else if (s == kSS || s == kSS2 || s == kSQpsi) use = use && k < col_wgs;
+          else if (s != kST0 && s != kST1) use = false;
+        }
+        v[u][s] = use ? load_agent(a.blockpart + (int64_t)s * nb + k) : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+#pragma unroll
+      for (int s = 0; s < kSlots; ++s) acc[s] += v[u][s];
+  }
+  if (is_iter(MODE)) {
+    double w[8] = {acc[kSR], acc[kSR2], acc[kSPphi], acc[kSS],
+                   acc[kSS2], acc[kSQpsi], acc[kST0], acc[kST1]};
+    wave_sum_n(w);
+    acc[kSR] = w[0];
+    acc[kSR2] = w[1];
+    acc[kSPphi] = w[2];
+    acc[kSS] = w[3];
+    acc[kSS2] = w[4];
+    acc[kSQpsi] = w[5];
+    acc[kST0] = w[6];
+    acc[kST1] = w[7];
+  } else {
+    wave_sum_n(acc);
+  }
+  if (lane != 0) return;
 
   DevState* st = a.st;
   const int64_t m = a.g.m, n = a.g.n;
   const double mn = (double)(m + n);
-  const double rho = st->rho;
+  const double rho = sv.rho;
   const uint64_t now = wall_clock64();
   if (is_iter(MODE)) {
     // kIterB has no <C,X> and no dual residual (C is not read): it records
     // NaN for them and can only stop at max_iter.
     const double beta = acc[kSR] / mn;
-    const double alpha = st->alpha;
+    const double alpha = sv.alpha;
     const double cc = 2.0 * beta - alpha;
     const double cphi = cc / (double)n, cpsi = cc / (double)m;
     const double nan = __builtin_nan("");
     const double pobj = MODE == kIterB ? nan : acc[kST0];
-    const double dobj = (acc[kSPphi] + cphi * st->sum_p + acc[kSQpsi] + cpsi * st->sum_q) / rho;
+    const double dobj = (acc[kSPphi] + cphi * sv.sum_p + acc[kSQpsi] + cpsi * sv.sum_q) / rho;
     const double gap = fabs(pobj - dobj);
     const double rp = sqrt(acc[kSR2] + acc[kSS2]);
     const double rd = MODE == kIterB ? nan : sqrt(acc[kST1]) / rho;
-    const double ep = rp / fmax(st->norm_pq, 1e-300);
-    const double ed = rd / fmax(st->norm_c, 1e-300);
+    const double ep = rp / fmax(sv.norm_pq, 1e-300);
+    const double ed = rd / fmax(sv.norm_c, 1e-300);
     const double eg = gap / fmax(fmax(fabs(pobj), fabs(dobj)), 1e-300);
-    const double test = st->tol_mode ? fmax(rp, fmax(rd, gap)) : fmax(ep, fmax(ed, eg));
-    const int64_t k = st->iter + 1;
-    st->alpha = alpha - beta;
+    const double test = sv.tol_mode ? fmax(rp, fmax(rd, gap)) : fmax(ep, fmax(ed, eg));
+    const int64_t k = sv.iter + 1;
+    const double alpha_next = alpha - beta;
+    st->alpha = alpha_next;
     st->cphi = cphi;
     st->cpsi = cpsi;
     st->iter = k;
@@ -251,24 +342,25 @@ __device__ void finish_global(const SweepArgs& a, int nb, double (&red)[kSlots][
     st->rd = rd;
     st->gap = gap;
     st->test = test;
-    double* tr = a.trace + ((k - 1) % a.trace_cap) * kTraceWidth;
+    const int64_t slot = k - 1 < a.trace_cap ? k - 1 : (k - 1) % a.trace_cap;
+    double* tr = a.trace + slot * kTraceWidth;
     tr[0] = pobj;
     tr[1] = dobj;
     tr[2] = rp;
     tr[3] = rd;
     tr[4] = gap;
     tr[5] = test;
-    tr[6] = (double)(now - st->t_start) / a.wall_rate;
+    tr[6] = (double)(now - sv.t_start) / a.wall_rate;
     tr[7] = (double)k;
     int done = 0, status = 0;
-    if ((MODE != kIterB && !finite_d(test)) || !finite_d(st->alpha) || !finite_d(cc) ||
+    if ((MODE != kIterB && !finite_d(test)) || !finite_d(alpha_next) || !finite_d(cc) ||
         !finite_d(rp)) {
       done = 1;
       status = -3;
-    } else if (MODE != kIterB && test <= st->tol) {
+    } else if (MODE != kIterB && test <= sv.tol) {
       done = 1;
       status = 0;
-    } else if (k >= st->max_iter) {
+    } else if (k >= sv.max_iter) {
       done = 1;
       status = 1;
     }
@@ -286,8 +378,8 @@ __device__ void finish_global(const SweepArgs& a, int nb, double (&red)[kSlots][
     st->f_rp = sqrt(acc[kSR2] + acc[kSS2]);
     st->f_rd = sqrt(acc[kST1]) / rho;
     st->f_gap = fabs(pobj - dobj);
-    st->f_eps_p = st->f_rp / fmax(st->norm_pq, 1e-300);
-    st->f_eps_d = st->f_rd / fmax(st->norm_c, 1e-300);
+    st->f_eps_p = st->f_rp / fmax(sv.norm_pq, 1e-300);
+    st->f_eps_d = st->f_rd / fmax(sv.norm_c, 1e-300);
     st->f_eps_g = st->f_gap / fmax(fmax(fabs(pobj), fabs(dobj)), 1e-300);
   } else {
     st->alpha = acc[kSR] / mn;
@@ -307,64 +399,138 @@ __device__ void finish_global(const SweepArgs& a, int nb, double (&red)[kSlots][
   }
 }
 
+// Loads of a strided sequence (base[r * stride], r0 <= r < r1) added into
+// `s` in ascending r, with the loads issued in masked batches of U so that a
+// short sequence costs one memory latency.
+template <int U, typename V, int CW>
+__device__ __forceinline__ void sum_strided(const V* base, int64_t stride, int r0, int r1,
+                                            double (&s)[CW]) {
+  for (int rb = r0; rb < r1; rb += U) {
+    V v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = rb + u;
+      v[u] = r < r1 ? __builtin_nontemporal_load(base + (int64_t)r * stride) : V{};
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int e = 0; e < CW; ++e) s[e] += (double)v[u][e];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // The O(m+n) kernel.  Workgroups [0, col_wgs) own kAuxCols columns each: the
-// column partials are read as 16-byte chunks with the row blocks split over
+// column partials are read as 16-byte chunks with the row groups split over
 // G thread groups, then combined in LDS in a fixed order.  The remaining
-// workgroups own 256 rows each.  Every workgroup also sums a fixed slice of
-// the tile scalars.  The last workgroup to finish does the scalar steps.
+// workgroups own kAuxRows rows each, with the column strips' row partials
+// split over the four waves.  All loads are issued up front, in masked
+// batches, ahead of the stop flag's test.  Every scalar contribution (the
+// per-column or per-row terms and a fixed slice of the tile scalars) lives in
+// wave 0, which sums them with DPP, publishes them and takes part in the
+// last-workgroup election; the other waves leave after the loads.  Wave 0 of
+// the last workgroup does the scalar steps.
 // ---------------------------------------------------------------------------
 template <typename T, int MODE>
 __device__ __forceinline__ void aux_body(const SweepArgs& a, const int b, const int nb) {
   using P = typename PartialOf<T, MODE>::type;
   constexpr int CW = 16 / sizeof(P);      // columns per 16-byte chunk
   constexpr int NCH = kAuxCols / CW;      // chunks per workgroup
-  constexpr int G = kBlock / NCH;         // row-block groups
+  constexpr int G = kBlock / NCH;         // row-group groups
   using V = typename VecOf<P, CW>::type;
+  static_assert(G * kAuxCols >= kWaves * kAuxRows, "LDS buffer holds the row partials");
+  static_assert(kAuxCols <= kWave && kAuxRows == kWave, "wave 0 finishes the entries");
 
-  DevState* st = a.st;
-  if (is_iter(MODE) && st->done) return;
-
+  const StateIn sv = load_state(a.st);
   __shared__ double red2[G * kAuxCols];
-  __shared__ double red[kSlots][kWaves];
-  __shared__ int last;
 
+  const int64_t m = a.g.m, n = a.g.n;
+  const int col_wgs = (int)((n + kAuxCols - 1) / kAuxCols);
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const bool is_col = b < col_wgs;
+
+  // Stage 1: loads.  `idx` is the column (column workgroups, threads below
+  // kAuxCols) or row (row workgroups, wave 0) this thread finishes, else -1;
+  // `w0`, `w1` its marginal entry and its accumulator (or phi / psi, or the
+  // warm start).
+  int64_t idx = -1;
+  double w0 = 0.0, w1 = 0.0;
+  if (is_col) {
+    const int64_t j0 = (int64_t)b * kAuxCols;
+    const int ch = threadIdx.x % NCH, grp = threadIdx.x / NCH;
+    const int n_rg = a.g.n_rg;
+    const int r0 = (int)((int64_t)n_rg * grp / G), r1 = (int)((int64_t)n_rg * (grp + 1) / G);
+    const P* cp = static_cast<const P*>(a.colpart) + j0 + ch * CW;
+    double s[CW];
+#pragma unroll
+    for (int e = 0; e < CW; ++e) s[e] = 0.0;
+    sum_strided<8>(reinterpret_cast<const V*>(cp), a.g.ldcp / CW, r0, r1, s);
+#pragma unroll
+    for (int e = 0; e < CW; ++e) red2[grp * kAuxCols + ch * CW + e] = s[e];
+    const int64_t j = j0 + threadIdx.x;
+    if (threadIdx.x < kAuxCols && j < n) {
+      idx = j;
+      w0 = (double)static_cast<const T*>(a.q)[j];
+      if (is_iter(MODE)) w1 = a.b[j];
+      else if (is_final(MODE)) w1 = a.psi64[j];
+      else w1 = a.nu0 ? a.nu0[j] : 0.0;
+    }
+  } else {
+    const int64_t i = (int64_t)(b - col_wgs) * kAuxRows + lane;
+    double u[1] = {0.0};
+    if (i < m) {
+      const int n_ct = a.g.n_ct;
+      const int c0 = n_ct * wave / kWaves, c1 = n_ct * (wave + 1) / kWaves;
+      typedef P P1 __attribute__((ext_vector_type(1)));
+      sum_strided<8>(reinterpret_cast<const P1*>(static_cast<const P*>(a.rowpart) + i), m, c0, c1,
+                     u);
+      if (wave == 0) {
+        idx = i;
+        w0 = (double)static_cast<const T*>(a.p)[i];
+        if (is_iter(MODE)) w1 = a.a[i];
+        else if (is_final(MODE)) w1 = a.phi64[i];
+        else w1 = a.mu0 ? a.mu0[i] : 0.0;
+      }
+    }
+    red2[wave * kAuxRows + lane] = u[0];
+  }
   double acc[kSlots];
 #pragma unroll
   for (int s = 0; s < kSlots; ++s) acc[s] = 0.0;
-  const int64_t m = a.g.m, n = a.g.n;
-  const int col_wgs = (int)((n + kAuxCols - 1) / kAuxCols);
-  const double rho = st->rho;
-
-  if (b < col_wgs) {
-    const int64_t j0 = (int64_t)b * kAuxCols;
-    {
-      const int ch = threadIdx.x % NCH, grp = threadIdx.x / NCH;
-      const int n_rg = a.g.n_rg;
-      const int r0 = (int)((int64_t)n_rg * grp / G), r1 = (int)((int64_t)n_rg * (grp + 1) / G);
-      const P* cp = static_cast<const P*>(a.colpart) + j0 + ch * CW;
-      double s[CW];
+  if (wave == 0) {
+    // A fixed slice of the sweep's tile scalars, 4 tiles per lane in flight.
+    const int64_t nt = (int64_t)a.g.n_ct * a.g.n_rg;
+    const int64_t t0 = nt * b / nb, t1 = nt * (b + 1) / nb;
+    for (int64_t tb = t0; tb < t1; tb += 4 * kWave) {
+      double v0[4], v1[4];
 #pragma unroll
-      for (int e = 0; e < CW; ++e) s[e] = 0.0;
-#pragma unroll 8
-      for (int r = r0; r < r1; ++r) {
-        const V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(cp + (int64_t)r * a.g.ldcp));
-#pragma unroll
-        for (int e = 0; e < CW; ++e) s[e] += (double)v[e];
+      for (int u = 0; u < 4; ++u) {
+        const int64_t t = tb + u * kWave + lane;
+        v0[u] = t < t1 ? a.tiles[t * kTileSlots + kTs0] : 0.0;
+        v1[u] = t < t1 ? a.tiles[t * kTileSlots + kTs1] : 0.0;
       }
 #pragma unroll
-      for (int e = 0; e < CW; ++e) red2[grp * kAuxCols + ch * CW + e] = s[e];
+      for (int u = 0; u < 4; ++u) {
+        acc[kST0] += v0[u];
+        acc[kST1] += v1[u];
+      }
     }
-    __syncthreads();
-    const int64_t j = j0 + threadIdx.x;
-    if (threadIdx.x < kAuxCols && j < n) {
+  }
+  __syncthreads();
+  if (wave != 0 || (is_iter(MODE) && sv.done)) return;
+
+  // Stage 2 (wave 0): the per-entry steps.
+  const double rho = sv.rho;
+  if (idx >= 0) {
+    if (is_col) {
       double v = red2[threadIdx.x];
 #pragma unroll
       for (int g = 1; g < G; ++g) v += red2[g * kAuxCols + threadIdx.x];
-      const double qj = (double)static_cast<const T*>(a.q)[j];
+      const int64_t j = idx;
+      const double qj = w0;
       const double s = v - qj;
       if (is_iter(MODE)) {
-        const double bj = a.b[j];
+        const double bj = w1;
         const double ps = (bj - 2.0 * s) / (double)m;
         a.b[j] = bj - s;
         a.psi64[j] = ps;
@@ -373,13 +539,13 @@ __device__ __forceinline__ void aux_body(const SweepArgs& a, const int b, const 
         acc[kSS2] = s * s;
         acc[kSQpsi] = qj * ps;
       } else if (is_final(MODE)) {
-        const double ps = a.psi64[j] + st->cpsi;
+        const double ps = w1 + sv.cpsi;
         acc[kSS2] = s * s;
         acc[kSQpsi] = qj * ps;
         if (a.nu_out) a.nu_out[j] = ps / rho;
       } else {
-        const double ps0 = a.nu0 ? rho * a.nu0[j] : 0.0;
-        const double bj = v - qj + (double)m * ps0 + st->sum_phi0;
+        const double ps0 = rho * w1;
+        const double bj = v - qj + (double)m * ps0 + sv.sum_phi0;
         a.b[j] = bj;
         a.psi64[j] = ps0;
         static_cast<T*>(a.psiT)[j] = (T)ps0;
@@ -389,17 +555,15 @@ __device__ __forceinline__ void aux_body(const SweepArgs& a, const int b, const 
         acc[kSNeg] = qj < 0.0 ? 1.0 : 0.0;
         acc[kSNonfin] = (!finite_d(qj) || !finite_d(ps0)) ? 1.0 : 0.0;
       }
-    }
-  } else {
-    const int64_t i = (int64_t)(b - col_wgs) * kBlock + threadIdx.x;
-    if (i < m) {
-      const P* rp = static_cast<const P*>(a.rowpart);
-      double u = 0.0;
-      for (int c = 0; c < a.g.n_ct; ++c) u += (double)rp[(int64_t)c * m + i];
-      const double pi = (double)static_cast<const T*>(a.p)[i];
+    } else {
+      double u = red2[lane];
+#pragma unroll
+      for (int w = 1; w < kWaves; ++w) u += red2[w * kAuxRows + lane];
+      const int64_t i = idx;
+      const double pi = w0;
       const double r = u - pi;
       if (is_iter(MODE)) {
-        const double ai = a.a[i];
+        const double ai = w1;
         const double ph = (ai - 2.0 * r) / (double)n;
         a.a[i] = ai - r;
         a.phi64[i] = ph;
@@ -408,13 +572,13 @@ __device__ __forceinline__ void aux_body(const SweepArgs& a, const int b, const 
         acc[kSR2] = r * r;
         acc[kSPphi] = pi * ph;
       } else if (is_final(MODE)) {
-        const double ph = a.phi64[i] + st->cphi;
+        const double ph = w1 + sv.cphi;
         acc[kSR2] = r * r;
         acc[kSPphi] = pi * ph;
         if (a.mu_out) a.mu_out[i] = ph / rho;
       } else {
-        const double ph0 = a.mu0 ? rho * a.mu0[i] : 0.0;
-        const double ai = u - pi + (double)n * ph0 + st->sum_psi0;
+        const double ph0 = rho * w1;
+        const double ai = u - pi + (double)n * ph0 + sv.sum_psi0;
         a.a[i] = ai;
         a.phi64[i] = ph0;
         static_cast<T*>(a.phiT)[i] = (T)ph0;
@@ -427,29 +591,39 @@ __device__ __forceinline__ void aux_body(const SweepArgs& a, const int b, const 
     }
   }
 
-  // A fixed slice of the sweep's tile scalars.
-  {
-    const int64_t nt = (int64_t)a.g.n_ct * a.g.n_rg;
-    const int64_t t0 = nt * b / nb, t1 = nt * (b + 1) / nb;
-    for (int64_t t = t0 + threadIdx.x; t < t1; t += kBlock) {
-      acc[kST0] += a.tiles[t * kTileSlots + kTs0];
-      acc[kST1] += a.tiles[t * kTileSlots + kTs1];
+  // Publish this workgroup's sums (slot-major), then count it in; the
+  // release fence orders the stores before the count and the acquire fence
+  // of the last workgroup orders its loads after it.  In the iteration a
+  // workgroup holds three column (or row) sums and the two tile sums only.
+  unsigned prev = 0;
+  if (is_iter(MODE)) {
+    const int s0 = is_col ? kSS : kSR;
+    double w[5] = {is_col ? acc[kSS] : acc[kSR], is_col ? acc[kSS2] : acc[kSR2],
+                   is_col ? acc[kSQpsi] : acc[kSPphi], acc[kST0], acc[kST1]};
+    wave_sum_n(w);
+    if (lane == 0) {
+#pragma unroll
+      for (int e = 0; e < 3; ++e) store_agent(a.blockpart + (int64_t)(s0 + e) * nb + b, w[e]);
+      store_agent(a.blockpart + (int64_t)kST0 * nb + b, w[3]);
+      store_agent(a.blockpart + (int64_t)kST1 * nb + b, w[4]);
+    }
+  } else {
+    wave_sum_n(acc);
+    if (lane == 0) {
+#pragma unroll
+      for (int s = 0; s < kSlots; ++s) store_agent(a.blockpart + (int64_t)s * nb + b, acc[s]);
     }
   }
-
-  block_sum_slots(acc, red);
-  if (threadIdx.x == 0) {
-    for (int s = 0; s < kSlots; ++s) store_agent(a.blockpart + (int64_t)b * kSlots + s, acc[s]);
-    __threadfence();
-    const unsigned prev = atomicAdd(&st->counter, 1u);
-    last = prev == (unsigned)(nb - 1);
+  if (lane == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    prev = __hip_atomic_fetch_add(&a.st->counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  finish_global<MODE>(a, nb, red);
-  if (threadIdx.x == 0)
-    __hip_atomic_store(&st->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  prev = __builtin_amdgcn_readfirstlane(prev);
+  if (prev != (unsigned)(nb - 1)) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  finish_global<MODE>(a, sv, nb, col_wgs);
+  if (lane == 0)
+    __hip_atomic_store(&a.st->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <typename T, int MODE>
@@ -764,19 +938,30 @@ __global__ __launch_bounds__(kBlock) void prep_batch_kernel(const SweepArgs* __r
   prep_body(args[blockIdx.x]);
 }
 
+// Stream of a sweep launch, with optional events that hipExtLaunchKernel
+// stamps with the dispatch's own start and end times.
+struct Launch {
+  hipStream_t s;
+  hipEvent_t e0, e1;
+};
+
 template <typename T, int MODE, int VEC, int CH, int U, bool NT, int CM = kCostDense, int D = 1,
           bool RAGGED = false>
-hipError_t sweep_go(const SweepArgs& a, hipStream_t s) {
-  const int64_t tiles = (int64_t)a.g.n_ct * a.g.n_rg;
-  hipLaunchKernelGGL((sweep_kernel<T, MODE, VEC, CH, U, NT, CM, D, RAGGED>), dim3((unsigned)tiles),
-                     dim3(kBlock), 0, s, a);
+hipError_t sweep_go(const SweepArgs& a, const Launch& s) {
+  const dim3 grid((unsigned)((int64_t)a.g.n_ct * a.g.n_rg));
+  if (s.e0 || s.e1)
+    hipExtLaunchKernelGGL((sweep_kernel<T, MODE, VEC, CH, U, NT, CM, D, RAGGED>), grid,
+                          dim3(kBlock), 0, s.s, s.e0, s.e1, 0, a);
+  else
+    hipLaunchKernelGGL((sweep_kernel<T, MODE, VEC, CH, U, NT, CM, D, RAGGED>), grid, dim3(kBlock),
+                       0, s.s, a);
   return hipGetLastError();
 }
 
 // 16-byte path with n not a multiple of the vector width (masked last chunk):
 // 1 or 2 chunks, 4 rows in flight, cached or streaming.
 template <typename T, int MODE, int CM, int D>
-hipError_t sweep_ragged(const TileCfg& t, const SweepArgs& a, hipStream_t s) {
+hipError_t sweep_ragged(const TileCfg& t, const SweepArgs& a, const Launch& s) {
   constexpr int V = 16 / sizeof(T);
   if (t.vec != V || t.unroll != 4) return hipErrorInvalidValue;
   switch ((t.chunks == 2 ? 1 : 0) | (t.stream ? 2 : 0)) {
@@ -791,7 +976,7 @@ hipError_t sweep_ragged(const TileCfg& t, const SweepArgs& a, hipStream_t s) {
 // The iteration instantiates every tile variant; initialisation and the final
 // evaluation run once per solve and use the plain 4-row variant.
 template <typename T, int MODE>
-hipError_t sweep_dense(const TileCfg& t, const SweepArgs& a, hipStream_t s) {
+hipError_t sweep_dense(const TileCfg& t, const SweepArgs& a, const Launch& s) {
   constexpr int V = 16 / sizeof(T);
   if (t.ragged) return sweep_ragged<T, MODE, kCostDense, 1>(t, a, s);
   if (t.vec == 1) {
@@ -823,7 +1008,7 @@ hipError_t sweep_dense(const TileCfg& t, const SweepArgs& a, hipStream_t s) {
 // Non-dense cost sources (float32 only): 1 or 2 chunks, 4 rows in flight,
 // cached or streaming; the scalar path uses 4 chunks, cached.
 template <int MODE, int CM, int D>
-hipError_t sweep_cost(const TileCfg& t, const SweepArgs& a, hipStream_t s) {
+hipError_t sweep_cost(const TileCfg& t, const SweepArgs& a, const Launch& s) {
   if (t.ragged) return sweep_ragged<float, MODE, CM, D>(t, a, s);
   if (t.vec == 1) {
     if (t.chunks == 4) return sweep_go<float, MODE, 1, 4, 4, false, CM, D>(a, s);
@@ -841,7 +1026,7 @@ hipError_t sweep_cost(const TileCfg& t, const SweepArgs& a, hipStream_t s) {
 }
 
 template <typename T, int MODE>
-hipError_t sweep_mode(const TileCfg& t, const SweepArgs& a, hipStream_t s) {
+hipError_t sweep_mode(const TileCfg& t, const SweepArgs& a, const Launch& s) {
   if (a.cost_kind == kCostDense) return sweep_dense<T, MODE>(t, a, s);
   if constexpr (std::is_same<T, float>::value && !(MODE == kIterA || MODE == kIterB ||
                                                    MODE == kFinalW)) {
@@ -858,7 +1043,7 @@ hipError_t sweep_mode(const TileCfg& t, const SweepArgs& a, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t sweep_type(int mode, const TileCfg& t, const SweepArgs& a, hipStream_t s) {
+hipError_t sweep_type(int mode, const TileCfg& t, const SweepArgs& a, const Launch& s) {
   switch (mode) {
     case kIter: return sweep_mode<T, kIter>(t, a, s);
     case kInitPQ: return sweep_mode<T, kInitPQ>(t, a, s);
@@ -925,8 +1110,9 @@ hipError_t launch_aux(int dtype, int mode, const SweepArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_sweep(int dtype, int mode, const TileCfg& t, const SweepArgs& a,
-                        hipStream_t s) {
-  return dtype == 0 ? sweep_type<float>(mode, t, a, s) : sweep_type<double>(mode, t, a, s);
+                        hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  const Launch L{s, e0, e1};
+  return dtype == 0 ? sweep_type<float>(mode, t, a, L) : sweep_type<double>(mode, t, a, L);
 }
 
 namespace {

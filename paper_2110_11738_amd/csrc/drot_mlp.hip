@@ -52,8 +52,6 @@ __host__ __device__ inline bf16 to_bf16(float f) {
   return (bf16)(u >> 16);
 }
 
-__device__ inline float from_bf16(bf16 b) { return __uint_as_float((uint32_t)b << 16); }
-
 // ---------------------------------------------------------------------------
 // C[M x N] = alpha * op(A)[M x K] * op(B)[K x N] + beta * C, bfloat16 inputs,
 // float32 accumulation and output.  A is stored row-major as M x K (TA = 0)
