@@ -55,6 +55,40 @@ def upload(inst):
     return C, p, q
 
 
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "sweep_f32_4096_pmc.txt")
+
+
+def pmc_traffic(m, n):
+    """HBM bytes per sweep launch measured with rocprofv3 FETCH_SIZE and
+    WRITE_SIZE (scaled by a plain copy of known size), read from the profile
+    summary; None unless it covers this workload and the kernel sources still
+    hash to the values recorded with the counters."""
+    import hashlib
+    try:
+        lines = open(PMC_SUMMARY).read().splitlines()
+    except OSError:
+        return None
+    kv, hashes = {}, {}
+    for line in lines:
+        if not line or line.startswith("#"):
+            continue
+        parts = line.split()
+        if parts[0] == "source_sha256" and len(parts) == 3:
+            hashes[parts[1]] = parts[2]
+        else:
+            kv[parts[0]] = " ".join(parts[1:])
+    if kv.get("workload") != f"{m}x{n} float32" or not hashes:
+        return None
+    for rel, h in hashes.items():
+        try:
+            with open(os.path.join(ROOT, rel), "rb") as fh:
+                if hashlib.sha256(fh.read()).hexdigest() != h:
+                    return None
+        except OSError:
+            return None
+    return float(kv["sweep_traffic_bytes"])
+
+
 def timed_run(ctx, bind, steps, warmup, flags):
     """Bind with `flags` (bind(flags, max_iter)), run `warmup` iterations,
     then time exactly `steps`.  Returns (seconds, average sweep ms or None,
@@ -89,18 +123,31 @@ def measure(ctx, bind, steps, warmup, flags=0):
     return {"seconds": secs, "seconds_eager": esecs, "sweep_ms": ms, "sweeps_timed": cnt}
 
 
-def dense_binder(ctx, C, p, q, rho, args):
+def dense_binder(ctx, C, p, q, rho, args, tile=None):
+    """bind(flags, max_iter) for the dense problem; `tile` (rows, chunks,
+    groups) overrides the command-line tile options."""
     import torch
     from paper_2110_11738_amd import drot
     X = torch.empty(C.shape, dtype=C.dtype, device=C.device)
+    rows, chunks, groups = tile if tile else (args.tile_rows, args.tile_chunks, args.tile_groups)
 
     def bind(flags, max_iter):
         prm = drot.make_params(rho, 0.0, max_iter, check_every=args.check_every, flags=flags,
-                               tile_rows=args.tile_rows, tile_chunks=args.tile_chunks,
+                               tile_rows=rows, tile_chunks=chunks,
                                tile_unroll=args.tile_unroll, cache_mode=args.cache_mode,
-                               tile_groups=args.tile_groups)
+                               tile_groups=groups)
         ctx.bind(C, p, q, X, prm)
+    bind.X = X
     return bind
+
+
+def tuned_tile(ctx, bind, iters=64):
+    """Run drot_tune on the bound problem; returns (rows, chunks, groups)."""
+    bind(0, 10)
+    best, us = ctx.tune(iters)
+    log(f"tuned tile: rows {best.tile_rows}, chunks {best.tile_chunks}, groups "
+        f"{best.tile_groups} ({us:.1f} us/iteration while tuning)")
+    return best.tile_rows, best.tile_chunks, best.tile_groups
 
 
 def cost_binder(ctx, m, n, cost, p, q, rho, keep):
@@ -247,6 +294,7 @@ def main():
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-skipc", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuned runs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration for profiles)")
     ap.add_argument("--check-every", type=int, default=64)
@@ -280,10 +328,17 @@ def main():
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
             "kernel": "sweep_kernel<float,iter>", "bytes_per_launch": alg_bytes,
+            "traffic_bytes_per_launch": None,
             "avg_launch_us": sweep_ms * 1e3, "launches_timed": cnt,
             "timing": "hipExtLaunchKernel start/stop events on every sweep of a second timed "
                       "region (eager launches, same workload and length)",
             "eager_iter_per_s": args.steps / r["seconds_eager"]}
+    tb = pmc_traffic(m, n)
+    if tb is not None:
+        # Counter bytes per launch over the same average launch duration.
+        roof["traffic"] = tb / (sweep_ms * 1e-3) / 1e9
+        roof["traffic_bytes_per_launch"] = tb
+        roof["traffic_source"] = os.path.relpath(PMC_SUMMARY, ROOT)
     log(f"{value:.1f} it/s ({1e3 * secs / args.steps:.4f} ms/it); sweep {sweep_ms * 1e3:.2f} us "
         f"-> {achieved:.0f} GB/s; eager {args.steps / r['seconds_eager']:.1f} it/s")
 
@@ -302,6 +357,17 @@ def main():
                    "check_every": args.check_every, "parallelism": "single GPU"},
         "roofline": roof,
     }
+
+    if not args.no_tune:
+        tile = tuned_tile(ctx, bind, 256)
+        rt = measure(ctx, dense_binder(ctx, C, p, q, inst.rho, args, tile), args.steps, args.warmup)
+        ach_t = alg_bytes / (rt["sweep_ms"] * 1e-3) / 1e9
+        out["tuned"] = {"tile_rows": tile[0], "tile_chunks": tile[1], "tile_groups": tile[2],
+                        "iter_per_s": args.steps / rt["seconds"],
+                        "avg_launch_us": rt["sweep_ms"] * 1e3, "achieved": ach_t,
+                        "frac": ach_t / HBM_PEAK_GBS}
+        log(f"tuned: {args.steps / rt['seconds']:.1f} it/s, sweep {rt['sweep_ms'] * 1e3:.2f} us "
+            f"-> {ach_t:.0f} GB/s")
 
     # ---- the paper's skip-C schedule on the same workload ---------------------
     if not args.no_skipc:
@@ -350,9 +416,10 @@ def main():
         rho_l = linst.rho
         del linst
         ksteps, kwarm = 40, 5
-        r = measure(ctx, dense_binder(ctx, C, p, q, rho_l, args), ksteps, kwarm)
-        secs_l, sweep_l, cnt_l = r["seconds"], r["sweep_ms"], r["sweeps_timed"]
         ab = BYTES_PER_ENTRY_F32 * L * L
+        binder = dense_binder(ctx, C, p, q, rho_l, args)
+        r = measure(ctx, binder, ksteps, kwarm)
+        secs_l, sweep_l, cnt_l = r["seconds"], r["sweep_ms"], r["sweeps_timed"]
         ach = ab / (sweep_l * 1e-3) / 1e9
         out["large"] = {"m": L, "n": L, "iter_per_s": ksteps / secs_l,
                         "ms_per_iter": 1e3 * secs_l / ksteps,
@@ -362,6 +429,17 @@ def main():
                                      "launches_timed": cnt_l}}
         log(f"{L}^2: {ksteps / secs_l:.1f} it/s, sweep {sweep_l * 1e3:.1f} us -> {ach:.0f} GB/s "
             f"({100 * ach / HBM_PEAK_GBS:.1f}% of peak)")
+        if not args.no_tune:
+            tile = tuned_tile(ctx, binder)
+            r = measure(ctx, dense_binder(ctx, C, p, q, rho_l, args, tile), ksteps, kwarm)
+            ach_t = ab / (r["sweep_ms"] * 1e-3) / 1e9
+            out["large"]["tuned"] = {"tile_rows": tile[0], "tile_chunks": tile[1],
+                                     "tile_groups": tile[2],
+                                     "iter_per_s": ksteps / r["seconds"],
+                                     "avg_launch_us": r["sweep_ms"] * 1e3, "achieved": ach_t,
+                                     "frac": ach_t / HBM_PEAK_GBS}
+            log(f"{L}^2 tuned: {ksteps / r['seconds']:.1f} it/s, sweep {r['sweep_ms'] * 1e3:.1f} us "
+                f"-> {ach_t:.0f} GB/s ({100 * ach_t / HBM_PEAK_GBS:.1f}% of peak)")
 
     if args.calibrate_copy:
         # A plain copy of known size: under `rocprofv3 --pmc FETCH_SIZE` (or

@@ -217,6 +217,23 @@ int drot_bind(drot_ctx *ctx, int64_t m, int64_t n, int dtype, const void *C, int
  * test (or max_iter) has fired are no-ops on the device. */
 int drot_iterate(drot_ctx *ctx, int64_t iters, void *stream);
 
+/* Autotune the tile variant of the sweep for the bound problem.  Not an
+ * operation of the paper: the sweep of Algorithm 1 (Section 3) can be tiled
+ * many ways, and which is fastest depends on the shape.  Each candidate --
+ * rows per block in {8, 16, 32} x {1, 2} 16-byte chunks per lane (on the
+ * scalar path 1 or 4 elements) x one or two row blocks per workgroup, with
+ * the bound cache_mode -- is bound (initialisation included), warmed up for
+ * one graph and timed over `iters` iterations (0 = four graphs; rounded up to
+ * whole graphs) with hipEvents on `stream`.  The fastest is then bound again
+ * with the caller's other parameters, ready for drot_iterate from iteration
+ * 0, and returned in *best (host; tile_rows, tile_chunks and tile_groups set).
+ * *us_per_iter (host, may be NULL) receives its time per iteration.
+ * X is overwritten by the trials, so the problem must have been bound with
+ * x0_mode = DROT_X0_PQ (else DROT_EUNSUPPORTED); DROT_ESTATE without a bound
+ * problem.  Blocks until done. */
+int drot_tune(drot_ctx *ctx, int64_t iters, drot_params *best, double *us_per_iter,
+              void *stream);
+
 /* Wait for `stream` and report progress: iterations done so far and whether
  * the stop flag is set (1) or not (0). */
 int drot_poll(drot_ctx *ctx, int64_t *iters_done, int32_t *stopped, void *stream);

@@ -32,7 +32,7 @@ EXPORTED = ("drot_version", "drot_strerror", "drot_last_error", "drot_ctx_create
             "drot_finish", "drot_get_trace", "drot_bind_cost", "drot_solve_cost",
             "drot_solve_batched", "drot_mlp_create", "drot_mlp_destroy", "drot_mlp_num_params",
             "drot_mlp_set_weights", "drot_mlp_get_weights", "drot_mlp_forward",
-            "drot_mlp_gradients", "drot_mlp_train_step")
+            "drot_mlp_gradients", "drot_mlp_train_step", "drot_tune")
 
 
 class Params(ctypes.Structure):
@@ -201,6 +201,15 @@ class Context:
 
     def iterate(self, iters: int, stream=None):
         return _check(lib().drot_iterate(self.handle, int(iters), _stream(stream)), allow=(OK,))
+
+    def tune(self, iters: int = 0, stream=None):
+        """drot_tune: time the tile variants on the bound problem and bind the
+        fastest.  Returns (params, microseconds per iteration)."""
+        best = Params()
+        us = ctypes.c_double()
+        _check(lib().drot_tune(self.handle, int(iters), ctypes.byref(best), ctypes.byref(us),
+                               _stream(stream)), allow=(OK,))
+        return best, us.value
 
     def poll(self, stream=None):
         k = ctypes.c_int64()

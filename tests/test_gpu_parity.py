@@ -247,6 +247,31 @@ def test_error_paths(ctx):
     torch.cuda.synchronize()
 
 
+def test_tune_binds_a_valid_variant(ctx):
+    """drot_tune times the tile variants and binds the fastest with the
+    caller's other parameters: the tuned iteration still matches the oracle,
+    and tuning refuses a problem bound with a given X_0 (it overwrites X)."""
+    torch = _torch()
+    from paper_2110_11738_amd import drot
+    inst = round_to(config_mixture_2d(13, 700, 900), np.float32)
+    C, p, q = _upload(inst, "float32")
+    X = torch.empty_like(C)
+    ctx.bind(C, p, q, X, drot.make_params(inst.rho, 0.0, 20, check_every=8))
+    best, us = ctx.tune(16)
+    assert best.tile_rows in (8, 16, 32) and best.tile_chunks in (1, 2)
+    assert us > 0 and best.max_iter == 20 and best.check_every == 8
+    ctx.iterate(20)
+    res = ctx.finish()
+    torch.cuda.synchronize()
+    R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=20)
+    assert res["iters"] == 20
+    assert _rel_max(X.double().cpu().numpy(), R.X) <= TOL["float32"][0]
+    ctx.bind(C, p, q, X, drot.make_params(inst.rho, 0.0, 20, x0_mode=drot.X0_GIVEN))
+    with pytest.raises(drot.DrotError) as e:
+        ctx.tune(8)
+    assert e.value.code == drot.EUNSUPPORTED
+
+
 @pytest.mark.parametrize("flags", ["graph", "eager"])
 def test_timed_sweeps_change_nothing(ctx, flags):
     """DROT_FLAG_TIME_SWEEP only adds hipEvents around the sweeps."""
