@@ -99,6 +99,16 @@ typedef enum { DROT_CACHE_AUTO = 0, DROT_CACHE_CACHED = 1, DROT_CACHE_STREAM = 2
  * C-reading iterations only (the other one has no <C,X> and no r_dual);
  * drot_finish restores X when the run ends on a C-reading iteration. */
 #define DROT_FLAG_SKIP_C 0x4
+/* Float32 problems: compensated sums in the sweep (the precision variant of
+ * the paper's kernel, Section 3, "Main kernel": there the row, column and
+ * cost sums are plain float32 sums).  Each lane keeps Neumaier-compensated
+ * float32 pairs for its row, column, <C,X> and dual-residual sums, and every
+ * later combination (lanes, waves, tiles, the aux kernel) is in float64, so
+ * each residual carries about one float32 rounding of its terms instead of
+ * one per addition.  X stays float32.  Float64 problems ignore the flag;
+ * combined with DROT_FLAG_SKIP_C it gives DROT_EUNSUPPORTED; ragged widths
+ * (n not a multiple of 4) use the 4-byte path. */
+#define DROT_FLAG_COMPENSATED 0x8
 
 typedef struct {
   double rho;          /* penalty parameter rho > 0 (the paper uses rho0/(m+n)) */

@@ -123,6 +123,10 @@ int choose_geometry(int dtype, int64_t m, int64_t n, const drot_cost* cost, cons
   const double cbytes = cost->kind == DROT_COST_DENSE ? (double)es
                         : cost->kind == DROT_COST_BF16 ? 2.0 : 0.0;
   const double bytes = (double)m * (double)n * ((double)es + cbytes);
+  g.tile.comp = (p->flags & DROT_FLAG_COMPENSATED) && dtype == DROT_F32;
+  // The compensated iteration has no masked-chunk variant: ragged widths take
+  // the scalar path.
+  if (g.tile.comp && n % V != 0) aligned = false;
   if (aligned) {
     // Measured on MI355X: while X and C fit in the last-level cache, cached
     // accesses with 2 chunks per lane and 32-row blocks; above it, streaming
@@ -133,11 +137,11 @@ int choose_geometry(int dtype, int64_t m, int64_t n, const drot_cost* cost, cons
     g.tile.chunks = p->tile_chunks > 0 ? p->tile_chunks : (g.tile.stream ? 1 : 2);
     g.tile.unroll = p->tile_unroll > 0 ? p->tile_unroll : 4;
     g.tile.ragged = n % V != 0;
-    if (g.tile.ragged) g.tile.unroll = 4;
+    if (g.tile.ragged || g.tile.comp) g.tile.unroll = 4;
   } else {
     // Scalar path: 4-byte/8-byte accesses, cached, 4 rows in flight.
     g.tile.vec = 1;
-    g.tile.chunks = p->tile_chunks == 1 ? 1 : 4;
+    g.tile.chunks = p->tile_chunks == 1 && !g.tile.comp ? 1 : 4;
     g.tile.unroll = 4;
     g.tile.stream = false;
   }
@@ -199,8 +203,11 @@ int validate(int64_t m, int64_t n, int dtype, const drot_cost* cost, const void*
   if (prm->x0_mode != DROT_X0_PQ && prm->x0_mode != DROT_X0_GIVEN)
     return fail(DROT_EINVAL, "unknown x0_mode %d", prm->x0_mode);
   if (prm->check_every < 0) return fail(DROT_EINVAL, "check_every must be >= 0");
-  if (prm->flags & ~(DROT_FLAG_NO_GRAPH | DROT_FLAG_TIME_SWEEP | DROT_FLAG_SKIP_C))
+  if (prm->flags &
+      ~(DROT_FLAG_NO_GRAPH | DROT_FLAG_TIME_SWEEP | DROT_FLAG_SKIP_C | DROT_FLAG_COMPENSATED))
     return fail(DROT_EINVAL, "unknown flags 0x%x", prm->flags);
+  if ((prm->flags & DROT_FLAG_SKIP_C) && (prm->flags & DROT_FLAG_COMPENSATED))
+    return fail(DROT_EUNSUPPORTED, "the skip-C schedule has no compensated variant");
   if (cost->kind != DROT_COST_DENSE && dtype != DROT_F32)
     return fail(DROT_EUNSUPPORTED, "bfloat16 and coordinate costs need a float32 problem");
   if (cost->kind != DROT_COST_DENSE && (prm->flags & DROT_FLAG_SKIP_C))
@@ -283,7 +290,7 @@ int iter_mode(const drot_ctx* c, int64_t idx) {
 // and end are the dispatch's own timestamps.
 int launch_iteration(drot_ctx* c, hipStream_t s, hipEvent_t e0, hipEvent_t e1, int mode) {
   HIP_TRY(launch_sweep(c->dtype, mode, c->geo.tile, c->sa, s, e0, e1));
-  HIP_TRY(launch_aux(c->dtype, mode, c->sa, s));
+  HIP_TRY(launch_aux(c->dtype, mode, c->sa, s, c->geo.tile.comp));
   return DROT_OK;
 }
 
@@ -308,7 +315,7 @@ int ensure_events(drot_ctx* c, int count) {
 int capture_one(drot_ctx* c, bool sweep, int mode, hipGraph_t* out) {
   HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
   hipError_t e = sweep ? launch_sweep(c->dtype, mode, c->geo.tile, c->sa, c->cap_stream)
-                       : launch_aux(c->dtype, mode, c->sa, c->cap_stream);
+                       : launch_aux(c->dtype, mode, c->sa, c->cap_stream, c->geo.tile.comp);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
   if (e != hipSuccess || e2 != hipSuccess) {

@@ -142,7 +142,8 @@ struct SweepArgs {
 struct TileCfg {
   int vec, chunks, unroll;
   bool stream;
-  bool ragged;  // 16-byte path with n not a multiple of vec (masked last chunk)
+  bool ragged;      // 16-byte path with n not a multiple of vec (masked last chunk)
+  bool comp = false;  // compensated per-lane sums, float64 partials (float32 iteration)
 };
 
 // Launchers (drot_kernels.hip).
@@ -150,7 +151,8 @@ struct TileCfg {
 // records the dispatch's own start and end times in those events.
 hipError_t launch_sweep(int dtype, int mode, const TileCfg& t, const SweepArgs& a,
                         hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-hipError_t launch_aux(int dtype, int mode, const SweepArgs& a, hipStream_t s);
+// `wide`: the float32 iteration's partials are float64 (compensated sweep).
+hipError_t launch_aux(int dtype, int mode, const SweepArgs& a, hipStream_t s, bool wide = false);
 hipError_t launch_prep(const SweepArgs& a, hipStream_t s);
 hipError_t launch_maxc(const SweepArgs& a, hipStream_t s);
 

@@ -431,9 +431,9 @@ __device__ __forceinline__ void sum_strided(const V* base, int64_t stride, int r
 // last-workgroup election; the other waves leave after the loads.  Wave 0 of
 // the last workgroup does the scalar steps.
 // ---------------------------------------------------------------------------
-template <typename T, int MODE>
+template <typename T, int MODE, bool WIDE = false>
 __device__ __forceinline__ void aux_body(const SweepArgs& a, const int b, const int nb) {
-  using P = typename PartialOf<T, MODE>::type;
+  using P = typename std::conditional<WIDE, double, typename PartialOf<T, MODE>::type>::type;
   constexpr int CW = 16 / sizeof(P);      // columns per 16-byte chunk
   constexpr int NCH = kAuxCols / CW;      // chunks per workgroup
   constexpr int G = kBlock / NCH;         // row-group groups
@@ -626,9 +626,9 @@ __device__ __forceinline__ void aux_body(const SweepArgs& a, const int b, const 
     __hip_atomic_store(&a.st->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool WIDE = false>
 __global__ __launch_bounds__(kBlock) void aux_kernel(SweepArgs a) {
-  aux_body<T, MODE>(a, blockIdx.x, gridDim.x);
+  aux_body<T, MODE, WIDE>(a, blockIdx.x, gridDim.x);
 }
 
 // Batched form: work item = (problem, aux workgroup of that problem).
@@ -640,6 +640,31 @@ __global__ __launch_bounds__(kBlock) void aux_batch_kernel(const SweepArgs* __re
   aux_body<T, MODE>(a, (int)w.y, (int)aux_workgroups(a.g.m, a.g.n));
 }
 
+// Per-lane accumulator of the sweep.  Plain: a running sum in the partial
+// type.  Compensated (float32 iteration with DROT_FLAG_COMPENSATED): a
+// Neumaier (improved Kahan-Babuska) pair of floats, so that a lane's sum over
+// its entries carries an error of about one rounding whatever its length; the
+// pair is handed on as s + c in float64, and every later combination
+// (across lanes, waves, tiles) is a float64 sum.
+template <typename P, bool KC>
+struct LaneAcc {
+  P v = 0;
+  template <typename X>
+  __device__ __forceinline__ void add(X x) { v += (P)x; }
+  __device__ __forceinline__ P get() const { return v; }
+};
+
+template <>
+struct LaneAcc<double, true> {
+  float s = 0.f, c = 0.f;
+  __device__ __forceinline__ void add(float x) {
+    const float t = s + x;
+    c += __builtin_fabsf(s) >= __builtin_fabsf(x) ? (s - t) + x : (x - t) + s;
+    s = t;
+  }
+  __device__ __forceinline__ double get() const { return (double)s + (double)c; }
+};
+
 // ---------------------------------------------------------------------------
 // The sweep.  A workgroup owns one column strip of W = 64 * VEC * CH columns
 // and the row blocks g, g + G, g + 2G, ... of `rows` rows each (G = n_rg row
@@ -650,9 +675,13 @@ __global__ __launch_bounds__(kBlock) void aux_batch_kernel(const SweepArgs* __re
 // owns CH chunks of VEC consecutive columns and keeps the loads of U rows in
 // flight.  Consecutive workgroups take consecutive strips of the same group.
 // ---------------------------------------------------------------------------
-template <typename T, int MODE, int VEC, int CH, int U, bool NT, int CM, int D, bool RAGGED>
+template <typename T, int MODE, int VEC, int CH, int U, bool NT, int CM, int D, bool RAGGED,
+          bool KC = false>
 __device__ __forceinline__ void sweep_body(const SweepArgs& a, const int ct, const int rg) {
-  using P = typename PartialOf<T, MODE>::type;
+  static_assert(!KC || (std::is_same<T, float>::value && MODE == kIter),
+                "compensated sums: float32 plain iteration only");
+  using P = typename std::conditional<KC, double, typename PartialOf<T, MODE>::type>::type;
+  using L = LaneAcc<P, KC>;
   using A = typename std::conditional<is_final(MODE), double, T>::type;
   constexpr int CPL = VEC * CH;
   constexpr int W = kWave * CPL;
@@ -728,12 +757,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a, const int ct, con
     rhoT = (T)st->rho;
   }
 
-  P colacc[CH][VEC];
-#pragma unroll
-  for (int c = 0; c < CH; ++c)
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) colacc[c][e] = 0;
-  P s0 = 0, s1 = 0;  // tile scalars (cost & dual, or |C|^2 & bad count)
+  L colacc[CH][VEC];
+  L s0, s1;  // tile scalars (cost & dual, or |C|^2 & bad count)
 
   P* __restrict__ rowpart = static_cast<P*>(a.rowpart);
 
@@ -786,7 +811,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a, const int ct, con
         if (is_iter(MODE)) rowv = static_cast<const T*>(a.phiT)[i] + shift;
         if (is_final(MODE)) rowv = a.phi64[i] + (double)shift;
         if (MODE == kInitPQ) rowv = static_cast<const T*>(a.p)[i];
-        P rsum = 0;
+        L rsum;
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
           if (ok[c]) {
@@ -807,7 +832,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a, const int ct, con
                 const A pc = is_final(MODE) ? rho * cij : mul_rounded<A>(rho, cij);
                 const A t = rowv + colv[c][e] - pc;
                 const A tp = t > (A)0 ? t : (A)0;
-                s1 += (P)(tp * tp);
+                s1.add(tp * tp);
                 if constexpr (MODE == kFinalW) {
                   // Restore X from W in the stored type, with the product the
                   // C-reading iteration subtracted.
@@ -822,19 +847,19 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a, const int ct, con
                   x = y > (A)0 ? y : (A)0;
                   outv[e] = MODE == kIterA ? (T)(x - pc) : (T)x;
                 }
-                s0 += (P)(cij * x);
+                s0.add(cij * x);
               } else {
                 const A cij = (A)cost(u, c, e);
                 if (MODE == kInitPQ) x = rowv * colv[c][e];
                 else x = (A)xv[u][c][e];
-                s0 += (P)((double)cij * (double)cij);
+                s0.add((double)cij * (double)cij);
                 const bool bad = !finite_d((double)cij) || !finite_d((double)x) ||
                                  (MODE == kInitX && x < (A)0);
-                s1 += bad ? (P)1 : (P)0;
+                s1.add(bad ? (P)1 : (P)0);
                 outv[e] = (T)x;
               }
-              rsum += (P)x;
-              colacc[c][e] += (P)x;
+              rsum.add(x);
+              colacc[c][e].add(x);
             }
             if (kWriteX) {
               if (!RAGGED || nv[c] == VEC) {
@@ -845,7 +870,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a, const int ct, con
             }
           }
         }
-        const P tot = wave_sum(rsum);
+        const P tot = wave_sum(rsum.get());
         if (lane == 0) rowpart[(int64_t)ct * m + i] = tot;
       }
     }
@@ -858,9 +883,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a, const int ct, con
 #pragma unroll
   for (int c = 0; c < CH; ++c)
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) sm[wave * W + c * kWave * VEC + lane * VEC + e] = colacc[c][e];
-  const P w0 = wave_sum(s0);
-  const P w1 = wave_sum(s1);
+    for (int e = 0; e < VEC; ++e)
+      sm[wave * W + c * kWave * VEC + lane * VEC + e] = colacc[c][e].get();
+  const P w0 = wave_sum(s0.get());
+  const P w1 = wave_sum(s1.get());
   if (lane == 0) {
     ssc[0][wave] = (double)w0;
     ssc[1][wave] = (double)w1;
@@ -889,10 +915,11 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a, const int ct, con
   }
 }
 
-template <typename T, int MODE, int VEC, int CH, int U, bool NT, int CM, int D, bool RAGGED>
+template <typename T, int MODE, int VEC, int CH, int U, bool NT, int CM, int D, bool RAGGED,
+          bool KC>
 __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a) {
-  sweep_body<T, MODE, VEC, CH, U, NT, CM, D, RAGGED>(a, blockIdx.x % a.g.n_ct,
-                                                      blockIdx.x / a.g.n_ct);
+  sweep_body<T, MODE, VEC, CH, U, NT, CM, D, RAGGED, KC>(a, blockIdx.x % a.g.n_ct,
+                                                          blockIdx.x / a.g.n_ct);
 }
 
 // Batched form: work item = (problem, workgroup of that problem's sweep).
@@ -946,16 +973,36 @@ struct Launch {
 };
 
 template <typename T, int MODE, int VEC, int CH, int U, bool NT, int CM = kCostDense, int D = 1,
-          bool RAGGED = false>
+          bool RAGGED = false, bool KC = false>
 hipError_t sweep_go(const SweepArgs& a, const Launch& s) {
   const dim3 grid((unsigned)((int64_t)a.g.n_ct * a.g.n_rg));
   if (s.e0 || s.e1)
-    hipExtLaunchKernelGGL((sweep_kernel<T, MODE, VEC, CH, U, NT, CM, D, RAGGED>), grid,
+    hipExtLaunchKernelGGL((sweep_kernel<T, MODE, VEC, CH, U, NT, CM, D, RAGGED, KC>), grid,
                           dim3(kBlock), 0, s.s, s.e0, s.e1, 0, a);
   else
-    hipLaunchKernelGGL((sweep_kernel<T, MODE, VEC, CH, U, NT, CM, D, RAGGED>), grid, dim3(kBlock),
-                       0, s.s, a);
+    hipLaunchKernelGGL((sweep_kernel<T, MODE, VEC, CH, U, NT, CM, D, RAGGED, KC>), grid,
+                       dim3(kBlock), 0, s.s, a);
   return hipGetLastError();
+}
+
+// The compensated float32 iteration: 16-byte path with 1 or 2 chunks, 4 rows
+// in flight, cached or streaming; the scalar path with 4 chunks (which the
+// host also uses for ragged widths).
+template <int CM, int D>
+hipError_t sweep_comp(const TileCfg& t, const SweepArgs& a, const Launch& s) {
+  if (t.ragged || t.unroll != 4) return hipErrorInvalidValue;
+  if (t.vec == 1) {
+    if (t.chunks != 4) return hipErrorInvalidValue;
+    return sweep_go<float, kIter, 1, 4, 4, false, CM, D, false, true>(a, s);
+  }
+  if (t.vec != 4) return hipErrorInvalidValue;
+  switch ((t.chunks == 2 ? 1 : 0) | (t.stream ? 2 : 0)) {
+    case 0: return sweep_go<float, kIter, 4, 1, 4, false, CM, D, false, true>(a, s);
+    case 1: return sweep_go<float, kIter, 4, 2, 4, false, CM, D, false, true>(a, s);
+    case 2: return sweep_go<float, kIter, 4, 1, 4, true, CM, D, false, true>(a, s);
+    case 3: return sweep_go<float, kIter, 4, 2, 4, true, CM, D, false, true>(a, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 // 16-byte path with n not a multiple of the vector width (masked last chunk):
@@ -1027,6 +1074,21 @@ hipError_t sweep_cost(const TileCfg& t, const SweepArgs& a, const Launch& s) {
 
 template <typename T, int MODE>
 hipError_t sweep_mode(const TileCfg& t, const SweepArgs& a, const Launch& s) {
+  if (t.comp) {
+    if constexpr (std::is_same<T, float>::value && MODE == kIter) {
+      switch (a.cost_kind) {
+        case kCostDense: return sweep_comp<kCostDense, 1>(t, a, s);
+        case kCostBF16: return sweep_comp<kCostBF16, 1>(t, a, s);
+        case kCostCoords:
+          if (a.dim == 1) return sweep_comp<kCostCoords, 1>(t, a, s);
+          if (a.dim == 2) return sweep_comp<kCostCoords, 2>(t, a, s);
+          if (a.dim == 3) return sweep_comp<kCostCoords, 3>(t, a, s);
+      }
+      return hipErrorInvalidValue;
+    }
+    // Initialisation and the final evaluation already accumulate in float64.
+    if constexpr (MODE == kIter || MODE == kIterA || MODE == kIterB) return hipErrorInvalidValue;
+  }
   if (a.cost_kind == kCostDense) return sweep_dense<T, MODE>(t, a, s);
   if constexpr (std::is_same<T, float>::value && !(MODE == kIterA || MODE == kIterB ||
                                                    MODE == kFinalW)) {
@@ -1088,8 +1150,14 @@ __global__ __launch_bounds__(kBlock) void maxc_kernel(SweepArgs a) {
 }
 
 template <typename T>
-hipError_t aux_type(int mode, const SweepArgs& a, hipStream_t s) {
+hipError_t aux_type(int mode, bool wide, const SweepArgs& a, hipStream_t s) {
   const dim3 grid((unsigned)aux_workgroups(a.g.m, a.g.n));
+  if (wide && std::is_same<T, float>::value) {
+    // Float64 partials of the compensated float32 iteration.
+    if (mode != kIter) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((aux_kernel<T, kIter, true>), grid, dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+  }
   switch (mode) {
     case kIter:
     case kIterA: hipLaunchKernelGGL((aux_kernel<T, kIter>), grid, dim3(kBlock), 0, s, a); break;
@@ -1105,8 +1173,8 @@ hipError_t aux_type(int mode, const SweepArgs& a, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_aux(int dtype, int mode, const SweepArgs& a, hipStream_t s) {
-  return dtype == 0 ? aux_type<float>(mode, a, s) : aux_type<double>(mode, a, s);
+hipError_t launch_aux(int dtype, int mode, const SweepArgs& a, hipStream_t s, bool wide) {
+  return dtype == 0 ? aux_type<float>(mode, wide, a, s) : aux_type<double>(mode, wide, a, s);
 }
 
 hipError_t launch_sweep(int dtype, int mode, const TileCfg& t, const SweepArgs& a,

@@ -22,7 +22,7 @@ EINVAL, EMASS, ENONFINITE, ENOMEM, EDEVICE, EUNSUPPORTED, ESTATE = -1, -2, -3, -
 F32, F64 = 0, 1
 TOL_RELATIVE, TOL_ABSOLUTE = 0, 1
 X0_PQ, X0_GIVEN = 0, 1
-FLAG_NO_GRAPH, FLAG_TIME_SWEEP, FLAG_SKIP_C = 0x1, 0x2, 0x4
+FLAG_NO_GRAPH, FLAG_TIME_SWEEP, FLAG_SKIP_C, FLAG_COMPENSATED = 0x1, 0x2, 0x4, 0x8
 CACHE_AUTO, CACHE_CACHED, CACHE_STREAM = 0, 1, 2
 COST_DENSE, COST_BF16, COST_COORDS = 0, 1, 2
 TRACE_FIELDS = ("pobj", "dobj", "r_primal", "r_dual_lag", "gap", "test", "seconds", "k")

@@ -39,8 +39,10 @@ def log(msg):
     print(f"[warmstart] {msg}", file=sys.stderr, flush=True)
 
 
-def rho_grid() -> float:
-    return (1.0 / math.log(N)) / (2 * N)
+def rho_grid(rho0: float | None = None) -> float:
+    """rho = rho0 / (m + n); rho0 = 1 / ln m unless given."""
+    r0 = 1.0 / math.log(N) if rho0 is None else rho0
+    return r0 / (2 * N)
 
 
 def features(ps: np.ndarray, qs: np.ndarray) -> np.ndarray:
@@ -61,13 +63,15 @@ def make_pairs(count: int, split: int, start: int = 0):
     return ps, qs
 
 
-def solve_pairs(ctx, C, ps, qs, tol=1e-4, max_iter=500_000, mu0=None, nu0=None, chunk=512):
-    """Solve every pair with the batched GPU solver (shared cost matrix).
-    Returns mu, nu (float64, per pair), iterations, device seconds, objectives."""
+def solve_pairs(ctx, C, ps, qs, tol=1e-4, max_iter=500_000, mu0=None, nu0=None, chunk=128,
+                rho0=None):
+    """Solve every pair with the batched GPU solver (shared cost matrix), in
+    chunks of `chunk` problems.  Returns mu, nu (float64, per pair),
+    iterations, device seconds, objectives, statuses."""
     import torch
     dev = C.device
     out_mu, out_nu, iters, secs, objs, status = [], [], [], [], [], []
-    rho = rho_grid()
+    rho = rho_grid(rho0)
     for s in range(0, len(ps), chunk):
         probs = []
         for k in range(s, min(s + chunk, len(ps))):
@@ -106,6 +110,8 @@ def train(net, X, T, epochs: int, batch: int, lr: float, seed: int = 0):
             idx = order[b * batch:(b + 1) * batch]
             tot += net.train_step(Xd[idx].contiguous(), Td[idx].contiguous(), lr)
         losses.append(tot / max(nb, 1))
+        if ep % 10 == 0 or ep == epochs - 1:
+            log(f"epoch {ep}: loss {losses[-1]:.4e}")
     return losses
 
 
@@ -123,18 +129,57 @@ def predict(net, X, batch: int):
     return Y[:, :N], Y[:, N:]
 
 
+def canonical(Cn: np.ndarray, mu: np.ndarray, nu: np.ndarray):
+    """Double c-transform of each pair: nu' = min_i (C_i. - mu_i), then
+    mu' = min_j (C_.j - nu'_j).  The result is dual feasible, no worse than
+    (mu, nu) on the LP dual, equal to it where the optimal duals are unique,
+    and fixes the values where they are not (cells without mass) to the
+    c-concave extension, which is a function of the problem rather than of
+    the solver's path."""
+    mu2 = np.empty_like(mu)
+    nu2 = np.empty_like(nu)
+    for k in range(len(mu)):
+        nu2[k] = (Cn - mu[k][:, None]).min(axis=0)
+        mu2[k] = (Cn - nu2[k][None, :]).min(axis=1)
+    return mu2, nu2
+
+
+def solved_data(ctx, C, ps, qs, tol, rho0, path, tag):
+    """solve_pairs, cached in an .npz file (path may be None)."""
+    key = f"{tag}_"
+    if path and os.path.exists(path):
+        z = np.load(path)
+        if key + "mu" in z.files and len(z[key + "mu"]) == len(ps):
+            log(f"loaded {tag} solutions from {path}")
+            return tuple(z[key + f] for f in ("mu", "nu", "it", "sec", "obj", "st"))
+    out = solve_pairs(ctx, C, ps, qs, tol, rho0=rho0)
+    if path:
+        old = dict(np.load(path)) if os.path.exists(path) else {}
+        for f, v in zip(("mu", "nu", "it", "sec", "obj", "st"), out):
+            old[key + f] = v.astype(np.float32) if f in ("mu", "nu") else v
+        np.savez(path, **old)
+    return out
+
+
 def run(n_train: int, n_test: int, epochs: int, batch: int, lr: float, tol: float,
-        hidden: int = 512, seed: int = 0) -> dict:
+        hidden: int = 512, seed: int = 0, rho0: float | None = None, data: str | None = None,
+        canon: bool = True) -> dict:
     import torch
     ctx = drot.Context(0)
-    C = torch.tensor(grid_cost(SIDE), dtype=torch.float32, device="cuda")
+    Cn = grid_cost(SIDE)
+    C = torch.tensor(Cn, dtype=torch.float32, device="cuda")
     t0 = time.time()
     ps, qs = make_pairs(n_train, 0)
     pt, qt = make_pairs(n_test, 1)
     log(f"generated {n_train} + {n_test} pairs in {time.time() - t0:.1f}s")
     t0 = time.time()
-    mu, nu, it_train, _, _, st_train = solve_pairs(ctx, C, ps, qs, tol)
+    mu, nu, it_train, _, _, st_train = solved_data(ctx, C, ps, qs, tol, rho0, data, "train")
     t_data = time.time() - t0
+    mu, nu = mu.astype(np.float64), nu.astype(np.float64)
+    if canon:
+        t0 = time.time()
+        mu, nu = canonical(Cn, mu, nu)
+        log(f"canonical targets in {time.time() - t0:.1f}s")
     X = features(ps, qs)
     T = gauge_fix(mu, nu)
     net = drot.MLP(2 * N, hidden, 2 * N, max_batch=max(batch, 64), seed=seed)
@@ -143,20 +188,25 @@ def run(n_train: int, n_test: int, epochs: int, batch: int, lr: float, tol: floa
     t_train = time.time() - t0
     log(f"trained {epochs} epochs in {t_train:.1f}s, loss {losses[0]:.4e} -> {losses[-1]:.4e}")
     # held-out: cold vs warm (the warm solve falls back to cold if it fails)
-    mu_c, nu_c, it_c, s_c, obj_c, st_c = solve_pairs(ctx, C, pt, qt, tol)
+    mu_c, nu_c, it_c, s_c, obj_c, st_c = solved_data(ctx, C, pt, qt, tol, rho0, data, "test")
+    mu_c, nu_c = mu_c.astype(np.float64), nu_c.astype(np.float64)
     mu_hat, nu_hat = predict(net, features(pt, qt), max(batch, 64))
-    mu_w, nu_w, it_w, s_w, obj_w, st_w = solve_pairs(ctx, C, pt, qt, tol, mu0=mu_hat, nu0=nu_hat)
+    mu_w, nu_w, it_w, s_w, obj_w, st_w = solve_pairs(ctx, C, pt, qt, tol, mu0=mu_hat, nu0=nu_hat,
+                                                     rho0=rho0)
     fallback = st_w != 0
     it_w_eff = np.where(fallback, it_w + it_c, it_w)
     rel_obj = np.abs(obj_w - obj_c) / np.abs(obj_c)
-    Tt = gauge_fix(mu_c, nu_c)
+    Tt = gauge_fix(*(canonical(Cn, mu_c, nu_c) if canon else (mu_c, nu_c)))
     pred_err = float(np.sqrt(((np.concatenate([mu_hat, nu_hat], 1) - Tt) ** 2).mean()))
+    spread = float(np.sqrt(((Tt - Tt.mean(axis=0)) ** 2).mean()))
     report = {
         "train_pairs": n_train, "test_pairs": n_test, "epochs": epochs, "batch": batch, "lr": lr,
-        "tol": tol, "hidden": hidden, "seconds_data": t_data, "seconds_train": t_train,
+        "tol": tol, "hidden": hidden, "rho0": rho0 if rho0 is not None else 1.0 / math.log(N),
+        "rho": rho_grid(rho0), "canonical_targets": canon, "seconds_data": t_data,
+        "seconds_train": t_train,
         "train_iters_mean": float(it_train.mean()), "train_unconverged": int((st_train != 0).sum()),
         "loss_first": losses[0], "loss_last": losses[-1],
-        "test_rmse_duals": pred_err,
+        "test_rmse_duals": pred_err, "test_rmse_of_mean_predictor": spread,
         "cold_iters_mean": float(it_c.mean()), "cold_iters_median": float(np.median(it_c)),
         "warm_iters_mean": float(it_w_eff.mean()), "warm_iters_median": float(np.median(it_w_eff)),
         "cold_seconds_mean": float(s_c.mean()), "warm_seconds_mean": float(s_w.mean()),
@@ -178,8 +228,12 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--hidden", type=int, default=512)
+    ap.add_argument("--rho0", type=float, default=None, help="rho = rho0 / (m + n); default 1 / ln m")
+    ap.add_argument("--data", default=None, help=".npz cache of the solved training and test pairs")
+    ap.add_argument("--raw-targets", action="store_true", help="learn the solver's duals as returned")
     args = ap.parse_args()
-    rep = run(args.train, args.test, args.epochs, args.batch, args.lr, args.tol, args.hidden)
+    rep = run(args.train, args.test, args.epochs, args.batch, args.lr, args.tol, args.hidden,
+              rho0=args.rho0, data=args.data, canon=not args.raw_targets)
     print(json.dumps(rep), flush=True)
 
 

@@ -247,6 +247,65 @@ def test_error_paths(ctx):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("m,n,cache_mode", [(300, 520, 0), (257, 1030, 0), (300, 1024, 2)])
+def test_compensated_trajectory(ctx, m, n, cache_mode):
+    """DROT_FLAG_COMPENSATED changes only how the sweep's sums are formed:
+    the float32 trajectory still matches the oracle (16-byte path cached and
+    streaming, and a ragged width on the 4-byte path)."""
+    from paper_2110_11738_amd import drot
+    inst = round_to(config_mixture_2d(14, m, n), np.float32)
+    Xg, res, mu, nu = _run(ctx, inst, "float32", 25, flags=drot.FLAG_COMPENSATED,
+                           cache_mode=cache_mode, check_every=8)
+    R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=25)
+    assert res["iters"] == 25
+    assert _rel_max(Xg, R.X) <= TOL["float32"][0]
+    assert _rel_max(mu, R.mu) <= TOL["float32"][1]
+    assert abs(res["objective"] - R.objective) <= TOL["float32"][2] * abs(R.objective)
+
+
+def test_compensated_sums_are_more_accurate(ctx):
+    """The primal residual the iteration reports (from the sweep's own row and
+    column sums) against the exact float64 residual of the same float32 plan:
+    the compensated sums must cut the error of the plain float32 sums at
+    least threefold, down to a few float32 roundings."""
+    torch = _torch()
+    from paper_2110_11738_amd import drot
+    inst = round_to(config_mixture_2d(15, 1024, 1024), np.float32)
+    C, p, q = _upload(inst, "float32")
+    K = 3000
+    errs = {}
+    for name, flags in (("plain", 0), ("comp", drot.FLAG_COMPENSATED)):
+        X = torch.empty_like(C)
+        ctx.bind(C, p, q, X, drot.make_params(inst.rho, 0.0, K, check_every=64, flags=flags))
+        ctx.iterate(K)
+        ctx.finish()
+        rp_gpu = ctx.trace(K, 1)[0, 2]
+        Xh = X.double().cpu().numpy()
+        r = Xh.sum(axis=1) - inst.p
+        s_ = Xh.sum(axis=0) - inst.q
+        rp = float(np.sqrt((r * r).sum() + (s_ * s_).sum()))
+        errs[name] = abs(rp_gpu - rp) / rp
+    print(f"[compensated] rp relative error: plain {errs['plain']:.3e}, "
+          f"compensated {errs['comp']:.3e}", flush=True)
+    assert errs["comp"] * 3 <= errs["plain"] or errs["comp"] <= 1e-6
+    assert errs["comp"] <= 1e-4
+
+
+def test_compensated_flag_rules(ctx):
+    """Float64 ignores the flag (bit-identical result); with the skip-C
+    schedule it is refused."""
+    from paper_2110_11738_amd import drot
+    inst = config_small_fp64(3, 60, 70)
+    a = _run(ctx, inst, "float64", 30)
+    b = _run(ctx, inst, "float64", 30, flags=drot.FLAG_COMPENSATED)
+    np.testing.assert_array_equal(a[0], b[0])
+    C, p, q = _upload(round_to(inst, np.float32), "float32")
+    with pytest.raises(drot.DrotError) as e:
+        drot.solve(C, p, q, inst.rho, max_iter=4, ctx=ctx,
+                   flags=drot.FLAG_COMPENSATED | drot.FLAG_SKIP_C)
+    assert e.value.code == drot.EUNSUPPORTED
+
+
 def test_tune_binds_a_valid_variant(ctx):
     """drot_tune times the tile variants and binds the fastest with the
     caller's other parameters: the tuned iteration still matches the oracle,
