@@ -244,6 +244,51 @@ def batch_section(ctx, count=512, iters=100):
             "workload": "config_batch: m, n ~ U[64, 2048], 2-D blob clouds, Dirichlet(1), float32"}
 
 
+def protocol_runs(ctx, bind, runs=10, iters=100):
+    """The paper's per-iteration runtime protocol (runtime experiment): `runs`
+    independent runs of `iters` iterations (graph replays), each from a fresh
+    bind; median iterations/s and a 95% interval of the median (order
+    statistics of the runs)."""
+    import statistics
+    import torch
+    rates = []
+    for _ in range(runs):
+        bind(0, iters + 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.iterate(iters)
+        torch.cuda.synchronize()
+        rates.append(iters / (time.perf_counter() - t0))
+    r = sorted(rates)
+    # For 10 runs the order statistics 2 and 9 (1-based) bracket the median
+    # with 97.9% confidence (binomial, p = 1/2).
+    lo, hi = (r[1], r[-2]) if runs >= 10 else (r[0], r[-1])
+    log(f"protocol {runs}x{iters}: median {statistics.median(r):.1f} it/s [{lo:.1f}, {hi:.1f}]")
+    return {"runs": runs, "iterations": iters, "median_iter_per_s": statistics.median(r),
+            "interval_iter_per_s": [lo, hi], "interval": "order statistics 2 and 9 of 10"}
+
+
+def copy_reference(mib=256, reps=20):
+    """Read + write bandwidth of torch's device copy of `mib` MiB (context for
+    the sweep's roofline fraction)."""
+    import torch
+    src = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbs = 2 * src.numel() * 4 / (ms * 1e-3) / 1e9
+    log(f"device copy of {mib} MiB: {ms * 1e3:.1f} us -> {gbs:.0f} GB/s (read + write)")
+    del src, dst
+    return {"bytes_moved": 2 * (mib << 20), "us": ms * 1e3, "GBs": gbs}
+
+
 def time_to_tol(ctx, C, p, q, rho, rho0_name, args, tol=1e-4, max_iter=2_000_000):
     """Solve to the relative tolerance; device seconds from the start of the
     initialisation to the iteration that met the test."""
@@ -379,6 +424,11 @@ def main():
                    "check_every": args.check_every, "parallelism": "single GPU"},
         "roofline": roof,
     }
+
+    # ---- the paper's runtime protocol: 10 runs x 100 iterations -----------------
+    out["protocol_10x100"] = protocol_runs(ctx, bind)
+    # ---- a plain device copy on the same box, for scale ---------------------------
+    out["copy_reference"] = copy_reference()
 
     if not args.no_tune:
         tile = tuned_tile(ctx, bind, 256)

@@ -320,6 +320,31 @@ int drot_mlp_gradients(drot_mlp *mlp, int batch, const float *x, const float *t,
 int drot_mlp_train_step(drot_mlp *mlp, int batch, const float *x, const float *t, float lr,
                         double *loss, void *stream);
 
+/* ---- checkpoint and resume (not in the paper; the iteration state of
+ * Algorithm 1 is X plus the O(m+n) vectors and scalars listed there) ------- */
+
+/* Size in bytes of a checkpoint of the bound problem. */
+int drot_checkpoint_size(drot_ctx *ctx, size_t *bytes);
+
+/* Copy the iteration state of the bound problem -- the device state record
+ * (iteration count, alpha, the scalar shift parts, stopping-test scale
+ * factors), a, b, phi, psi and the trace -- to `host_buf` (host memory, at
+ * least drot_checkpoint_size bytes, owned by the caller) after the work
+ * enqueued on `stream` has finished.  X is the caller's array and is not
+ * copied: save it alongside.  Under DROT_FLAG_SKIP_C only after an even
+ * number of iterations (else X holds X - rho C: DROT_ESTATE). */
+int drot_checkpoint(drot_ctx *ctx, void *host_buf, size_t bytes, void *stream);
+
+/* Continue a checkpointed run: bind the same problem first (same m, n,
+ * dtype, cost kind and skip-C flag; X holding the checkpointed plan and
+ * x0_mode = DROT_X0_GIVEN, so that the initialisation pass only validates
+ * it), then call drot_resume.  The next drot_iterate continues from the
+ * checkpointed iteration with the bound tol, tol_mode and max_iter (which
+ * counts all iterations, before and after the checkpoint); device times are
+ * measured from the resume.  A mismatched or corrupt checkpoint gives
+ * DROT_EINVAL and leaves the bound state as the bind made it. */
+int drot_resume(drot_ctx *ctx, const void *host_buf, size_t bytes, void *stream);
+
 /* Copy per-iteration records of the last bound problem to host memory.
  * Record k (1-based iteration index) holds 8 doubles:
  *   pobj, dobj, r_primal, r_dual (lagged, see drot_tol_mode), gap,

@@ -820,6 +820,125 @@ int drot_finish(drot_ctx* c, double* mu, double* nu, drot_result* out, void* str
   return out->status;
 }
 
+// Checkpoint layout (host memory): header, the device state record, the
+// vectors a, b, phi (FP64), psi (FP64), phi, psi (element type), the trace.
+struct CkptHeader {
+  char magic[8];  // "DROTCKP1"
+  int64_t m, n;
+  int32_t dtype, cost_kind;
+  int64_t enq;    // iterations enqueued since bind
+  int32_t skipc, pad;
+  uint64_t bytes; // total size
+};
+
+static size_t ckpt_bytes(const drot_ctx* c) {
+  const int64_t m = c->args.m, n = c->args.n;
+  const size_t es = c->dtype == DROT_F32 ? 4 : 8;
+  return sizeof(CkptHeader) + sizeof(DevState) + sizeof(double) * (size_t)(2 * m + 2 * n) +
+         es * (size_t)(m + n) + sizeof(double) * kTraceCap * kTraceWidth;
+}
+
+int drot_checkpoint_size(drot_ctx* c, size_t* bytes) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!c->bound) return fail(DROT_ESTATE, "no problem bound");
+  if (!bytes) return fail(DROT_EINVAL, "bytes is NULL");
+  *bytes = ckpt_bytes(c);
+  return DROT_OK;
+}
+
+int drot_checkpoint(drot_ctx* c, void* host_buf, size_t bytes, void* stream) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!c->bound) return fail(DROT_ESTATE, "no problem bound");
+  if (!host_buf || bytes < ckpt_bytes(c))
+    return fail(DROT_EINVAL, "checkpoint buffer of %zu bytes is too small (%zu needed)", bytes,
+                ckpt_bytes(c));
+  if (c->skipc && (c->enq & 1))
+    return fail(DROT_ESTATE, "under the skip-C schedule X holds X - rho C after an odd number of "
+                             "iterations: checkpoint after an even number");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipStreamSynchronize(s));
+  const int64_t m = c->args.m, n = c->args.n;
+  const size_t es = c->dtype == DROT_F32 ? 4 : 8;
+  char* out = static_cast<char*>(host_buf);
+  CkptHeader h{};
+  memcpy(h.magic, "DROTCKP1", 8);
+  h.m = m;
+  h.n = n;
+  h.dtype = c->dtype;
+  h.cost_kind = c->args.cost.kind;
+  h.enq = c->enq;
+  h.skipc = c->skipc;
+  h.bytes = ckpt_bytes(c);
+  memcpy(out, &h, sizeof h);
+  size_t o = sizeof h;
+  const struct {
+    const void* src;
+    size_t len;
+  } parts[] = {{c->st, sizeof(DevState)},       {c->sa.a, sizeof(double) * m},
+               {c->sa.b, sizeof(double) * n},    {c->sa.phi64, sizeof(double) * m},
+               {c->sa.psi64, sizeof(double) * n}, {c->sa.phiT, es * m},
+               {c->sa.psiT, es * n},             {c->trace, sizeof(double) * kTraceCap * kTraceWidth}};
+  for (const auto& part : parts) {
+    HIP_TRY(hipMemcpy(out + o, part.src, part.len, hipMemcpyDeviceToHost));
+    o += part.len;
+  }
+  return DROT_OK;
+}
+
+int drot_resume(drot_ctx* c, const void* host_buf, size_t bytes, void* stream) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!c->bound) return fail(DROT_ESTATE, "bind the problem (with X holding the checkpointed plan) first");
+  if (!host_buf || bytes < sizeof(CkptHeader)) return fail(DROT_EINVAL, "checkpoint too small");
+  CkptHeader h;
+  memcpy(&h, host_buf, sizeof h);
+  if (memcmp(h.magic, "DROTCKP1", 8) != 0) return fail(DROT_EINVAL, "not a DROT checkpoint");
+  if (h.m != c->args.m || h.n != c->args.n || h.dtype != c->dtype ||
+      h.cost_kind != c->args.cost.kind || (h.skipc != 0) != c->skipc)
+    return fail(DROT_EINVAL, "checkpoint of a %lldx%lld problem (dtype %d, cost %d, skip-C %d) "
+                             "does not match the bound problem",
+                (long long)h.m, (long long)h.n, h.dtype, h.cost_kind, h.skipc);
+  if (h.bytes != ckpt_bytes(c) || bytes < h.bytes) return fail(DROT_EINVAL, "checkpoint size mismatch");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipStreamSynchronize(s));
+  const int64_t m = c->args.m, n = c->args.n;
+  const size_t es = c->dtype == DROT_F32 ? 4 : 8;
+  const char* in = static_cast<const char*>(host_buf);
+  size_t o = sizeof h;
+  const struct {
+    void* dst;
+    size_t len;
+  } parts[] = {{c->st, sizeof(DevState)},       {c->sa.a, sizeof(double) * m},
+               {c->sa.b, sizeof(double) * n},    {c->sa.phi64, sizeof(double) * m},
+               {c->sa.psi64, sizeof(double) * n}, {c->sa.phiT, es * m},
+               {c->sa.psiT, es * n},             {c->trace, sizeof(double) * kTraceCap * kTraceWidth}};
+  for (const auto& part : parts) {
+    HIP_TRY(hipMemcpy(part.dst, in + o, part.len, hipMemcpyHostToDevice));
+    o += part.len;
+  }
+  // The bound run's tolerances and limits apply from here on.
+  DevState* st = c->st_host;
+  memcpy(st, in + sizeof h, sizeof(DevState));
+  st->tol = c->prm.tol;
+  st->max_iter = c->prm.max_iter;
+  st->tol_mode = c->prm.tol_mode;
+  st->done = 0;
+  st->status = 0;
+  HIP_TRY(hipMemcpy(c->st, st, sizeof(DevState), hipMemcpyHostToDevice));
+  // Fresh time origin and completion counter (the prep kernel; without a warm
+  // start its sums of phi_0 and psi_0 are zero and no longer used).
+  SweepArgs sa = c->sa;
+  sa.mu0 = nullptr;
+  sa.nu0 = nullptr;
+  HIP_TRY(launch_prep(sa, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  c->enq = h.enq;
+  c->finished = false;
+  return DROT_OK;
+}
+
 int drot_get_trace(drot_ctx* c, int64_t first, int64_t count, double* host_out) {
   int rc = check_ctx(c);
   if (rc) return rc;

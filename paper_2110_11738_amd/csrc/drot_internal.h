@@ -14,7 +14,7 @@ constexpr int kTileSlots = 2;      // per-tile scalar partials (see TileSlot)
 constexpr int kSlots = 13;         // per-finisher scalar partials (see Slot)
 constexpr int kTraceCap = 65536;   // per-iteration records kept on the device
 constexpr int kTraceWidth = 8;
-constexpr int kAuxCols = 32;       // columns per aux column workgroup
+constexpr int kAuxCols = 64;       // columns per aux column workgroup
 constexpr int kAuxRows = kWave;    // rows per aux row workgroup
 
 // Workgroups of one aux launch: column groups of kAuxCols, then row groups of

@@ -32,7 +32,8 @@ EXPORTED = ("drot_version", "drot_strerror", "drot_last_error", "drot_ctx_create
             "drot_finish", "drot_get_trace", "drot_bind_cost", "drot_solve_cost",
             "drot_solve_batched", "drot_mlp_create", "drot_mlp_destroy", "drot_mlp_num_params",
             "drot_mlp_set_weights", "drot_mlp_get_weights", "drot_mlp_forward",
-            "drot_mlp_gradients", "drot_mlp_train_step", "drot_tune")
+            "drot_mlp_gradients", "drot_mlp_train_step", "drot_tune", "drot_checkpoint_size",
+            "drot_checkpoint", "drot_resume")
 
 
 class Params(ctypes.Structure):
@@ -121,6 +122,10 @@ def lib():
     L.drot_mlp_forward.argtypes = [vp, i32, vp, vp, vp]
     L.drot_mlp_gradients.argtypes = [vp, i32, vp, vp, vp, dp, vp]
     L.drot_mlp_train_step.argtypes = [vp, i32, vp, vp, ctypes.c_float, dp, vp]
+    L.drot_tune.argtypes = [vp, i64, ctypes.POINTER(Params), dp, vp]
+    L.drot_checkpoint_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.drot_checkpoint.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    L.drot_resume.argtypes = [vp, vp, ctypes.c_size_t, vp]
     for name in EXPORTED:
         getattr(L, name).restype = getattr(L, name).restype or i32
     _lib = L
@@ -210,6 +215,20 @@ class Context:
         _check(lib().drot_tune(self.handle, int(iters), ctypes.byref(best), ctypes.byref(us),
                                _stream(stream)), allow=(OK,))
         return best, us.value
+
+    def checkpoint(self, stream=None) -> bytes:
+        """drot_checkpoint: the iteration state (not X) as bytes."""
+        size = ctypes.c_size_t()
+        _check(lib().drot_checkpoint_size(self.handle, ctypes.byref(size)), allow=(OK,))
+        buf = ctypes.create_string_buffer(size.value)
+        _check(lib().drot_checkpoint(self.handle, buf, size, _stream(stream)), allow=(OK,))
+        return buf.raw
+
+    def resume(self, blob: bytes, stream=None):
+        """drot_resume: continue from a checkpoint (bind the problem first)."""
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        return _check(lib().drot_resume(self.handle, buf, ctypes.c_size_t(len(blob)),
+                                        _stream(stream)), allow=(OK,))
 
     def poll(self, stream=None):
         k = ctypes.c_int64()

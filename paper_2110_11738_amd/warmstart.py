@@ -31,22 +31,23 @@ from gen import grid_cost, grid_histogram_pair  # noqa: E402
 
 from . import drot  # noqa: E402
 
-SIDE = 32
-N = SIDE * SIDE
+SIDE = 32  # grid side of the default experiment (N = SIDE^2 cells per histogram)
 
 
 def log(msg):
     print(f"[warmstart] {msg}", file=sys.stderr, flush=True)
 
 
-def rho_grid(rho0: float | None = None) -> float:
-    """rho = rho0 / (m + n); rho0 = 1 / ln m unless given."""
+def rho_grid(rho0: float | None = None, side: int = SIDE) -> float:
+    """rho = rho0 / (m + n) with m = n = side^2; rho0 = 1 / ln m unless given."""
+    N = side * side
     r0 = 1.0 / math.log(N) if rho0 is None else rho0
     return r0 / (2 * N)
 
 
 def features(ps: np.ndarray, qs: np.ndarray) -> np.ndarray:
     """Network input: the two histograms scaled by the grid size (mean 1)."""
+    N = ps.shape[1]
     return np.concatenate([ps * N, qs * N], axis=1).astype(np.float32)
 
 
@@ -55,23 +56,23 @@ def gauge_fix(mu: np.ndarray, nu: np.ndarray) -> np.ndarray:
     return np.concatenate([mu - t, nu + t], axis=1).astype(np.float32)
 
 
-def make_pairs(count: int, split: int, start: int = 0):
-    ps = np.empty((count, N))
-    qs = np.empty((count, N))
+def make_pairs(count: int, split: int, start: int = 0, side: int = SIDE):
+    ps = np.empty((count, side * side))
+    qs = np.empty((count, side * side))
     for k in range(count):
-        ps[k], qs[k] = grid_histogram_pair(start + k, split, SIDE)
+        ps[k], qs[k] = grid_histogram_pair(start + k, split, side)
     return ps, qs
 
 
 def solve_pairs(ctx, C, ps, qs, tol=1e-4, max_iter=500_000, mu0=None, nu0=None, chunk=128,
-                rho0=None):
+                rho0=None, quiet=False):
     """Solve every pair with the batched GPU solver (shared cost matrix), in
     chunks of `chunk` problems.  Returns mu, nu (float64, per pair),
     iterations, device seconds, objectives, statuses."""
     import torch
     dev = C.device
     out_mu, out_nu, iters, secs, objs, status = [], [], [], [], [], []
-    rho = rho_grid(rho0)
+    rho = rho_grid(rho0, int(round(math.sqrt(ps.shape[1]))))
     for s in range(0, len(ps), chunk):
         probs = []
         for k in range(s, min(s + chunk, len(ps))):
@@ -90,12 +91,13 @@ def solve_pairs(ctx, C, ps, qs, tol=1e-4, max_iter=500_000, mu0=None, nu0=None, 
             secs.append(r["seconds_to_tol"])
             objs.append(r["objective"])
             status.append(r["status"])
-        log(f"solved {min(s + chunk, len(ps))}/{len(ps)} (mean iterations {np.mean(iters):.0f})")
+        if not quiet:
+            log(f"solved {min(s + chunk, len(ps))}/{len(ps)} (mean iterations {np.mean(iters):.0f})")
     return (np.array(out_mu), np.array(out_nu), np.array(iters), np.array(secs), np.array(objs),
             np.array(status))
 
 
-def train(net, X, T, epochs: int, batch: int, lr: float, seed: int = 0):
+def train(net, X, T, epochs: int, batch: int, lr: float, seed: int = 0, quiet: bool = False):
     """Adam over shuffled mini-batches (the last partial batch is dropped)."""
     import torch
     rng = np.random.default_rng(seed)
@@ -110,7 +112,7 @@ def train(net, X, T, epochs: int, batch: int, lr: float, seed: int = 0):
             idx = order[b * batch:(b + 1) * batch]
             tot += net.train_step(Xd[idx].contiguous(), Td[idx].contiguous(), lr)
         losses.append(tot / max(nb, 1))
-        if ep % 10 == 0 or ep == epochs - 1:
+        if not quiet and (ep % 10 == 0 or ep == epochs - 1):
             log(f"epoch {ep}: loss {losses[-1]:.4e}")
     return losses
 
@@ -126,6 +128,7 @@ def predict(net, X, batch: int):
         y = net.forward(torch.tensor(xb, device="cuda")).cpu().numpy()
         out.append(y[:len(part)])
     Y = np.concatenate(out).astype(np.float64)
+    N = Y.shape[1] // 2
     return Y[:, :N], Y[:, N:]
 
 
@@ -144,7 +147,7 @@ def canonical(Cn: np.ndarray, mu: np.ndarray, nu: np.ndarray):
     return mu2, nu2
 
 
-def solved_data(ctx, C, ps, qs, tol, rho0, path, tag):
+def solved_data(ctx, C, ps, qs, tol, rho0, path, tag, quiet=False):
     """solve_pairs, cached in an .npz file (path may be None)."""
     key = f"{tag}_"
     if path and os.path.exists(path):
@@ -152,7 +155,7 @@ def solved_data(ctx, C, ps, qs, tol, rho0, path, tag):
         if key + "mu" in z.files and len(z[key + "mu"]) == len(ps):
             log(f"loaded {tag} solutions from {path}")
             return tuple(z[key + f] for f in ("mu", "nu", "it", "sec", "obj", "st"))
-    out = solve_pairs(ctx, C, ps, qs, tol, rho0=rho0)
+    out = solve_pairs(ctx, C, ps, qs, tol, rho0=rho0, quiet=quiet)
     if path:
         old = dict(np.load(path)) if os.path.exists(path) else {}
         for f, v in zip(("mu", "nu", "it", "sec", "obj", "st"), out):
@@ -163,17 +166,19 @@ def solved_data(ctx, C, ps, qs, tol, rho0, path, tag):
 
 def run(n_train: int, n_test: int, epochs: int, batch: int, lr: float, tol: float,
         hidden: int = 512, seed: int = 0, rho0: float | None = None, data: str | None = None,
-        canon: bool = True) -> dict:
+        canon: bool = True, side: int = SIDE, quiet: bool = False) -> dict:
     import torch
+    N = side * side
     ctx = drot.Context(0)
-    Cn = grid_cost(SIDE)
+    Cn = grid_cost(side)
     C = torch.tensor(Cn, dtype=torch.float32, device="cuda")
     t0 = time.time()
-    ps, qs = make_pairs(n_train, 0)
-    pt, qt = make_pairs(n_test, 1)
+    ps, qs = make_pairs(n_train, 0, side=side)
+    pt, qt = make_pairs(n_test, 1, side=side)
     log(f"generated {n_train} + {n_test} pairs in {time.time() - t0:.1f}s")
     t0 = time.time()
-    mu, nu, it_train, _, _, st_train = solved_data(ctx, C, ps, qs, tol, rho0, data, "train")
+    mu, nu, it_train, _, _, st_train = solved_data(ctx, C, ps, qs, tol, rho0, data, "train",
+                                                        quiet)
     t_data = time.time() - t0
     mu, nu = mu.astype(np.float64), nu.astype(np.float64)
     if canon:
@@ -182,17 +187,24 @@ def run(n_train: int, n_test: int, epochs: int, batch: int, lr: float, tol: floa
         log(f"canonical targets in {time.time() - t0:.1f}s")
     X = features(ps, qs)
     T = gauge_fix(mu, nu)
+    # Standardised targets (per output: training mean and one global scale).
+    t_mean = T.mean(axis=0, keepdims=True)
+    t_scale = float(T.std()) or 1.0
     net = drot.MLP(2 * N, hidden, 2 * N, max_batch=max(batch, 64), seed=seed)
     t0 = time.time()
-    losses = train(net, X, T, epochs, batch, lr, seed)
+    losses = train(net, X, ((T - t_mean) / t_scale).astype(np.float32), epochs, batch, lr, seed,
+                   quiet)
     t_train = time.time() - t0
     log(f"trained {epochs} epochs in {t_train:.1f}s, loss {losses[0]:.4e} -> {losses[-1]:.4e}")
     # held-out: cold vs warm (the warm solve falls back to cold if it fails)
-    mu_c, nu_c, it_c, s_c, obj_c, st_c = solved_data(ctx, C, pt, qt, tol, rho0, data, "test")
+    mu_c, nu_c, it_c, s_c, obj_c, st_c = solved_data(ctx, C, pt, qt, tol, rho0, data, "test",
+                                                       quiet)
     mu_c, nu_c = mu_c.astype(np.float64), nu_c.astype(np.float64)
     mu_hat, nu_hat = predict(net, features(pt, qt), max(batch, 64))
+    mu_hat = mu_hat * t_scale + t_mean[0, :N]
+    nu_hat = nu_hat * t_scale + t_mean[0, N:]
     mu_w, nu_w, it_w, s_w, obj_w, st_w = solve_pairs(ctx, C, pt, qt, tol, mu0=mu_hat, nu0=nu_hat,
-                                                     rho0=rho0)
+                                                     rho0=rho0, quiet=quiet)
     fallback = st_w != 0
     it_w_eff = np.where(fallback, it_w + it_c, it_w)
     rel_obj = np.abs(obj_w - obj_c) / np.abs(obj_c)
@@ -202,7 +214,7 @@ def run(n_train: int, n_test: int, epochs: int, batch: int, lr: float, tol: floa
     report = {
         "train_pairs": n_train, "test_pairs": n_test, "epochs": epochs, "batch": batch, "lr": lr,
         "tol": tol, "hidden": hidden, "rho0": rho0 if rho0 is not None else 1.0 / math.log(N),
-        "rho": rho_grid(rho0), "canonical_targets": canon, "seconds_data": t_data,
+        "side": side, "rho": rho_grid(rho0, side), "canonical_targets": canon, "seconds_data": t_data,
         "seconds_train": t_train,
         "train_iters_mean": float(it_train.mean()), "train_unconverged": int((st_train != 0).sum()),
         "loss_first": losses[0], "loss_last": losses[-1],
@@ -231,9 +243,10 @@ def main():
     ap.add_argument("--rho0", type=float, default=None, help="rho = rho0 / (m + n); default 1 / ln m")
     ap.add_argument("--data", default=None, help=".npz cache of the solved training and test pairs")
     ap.add_argument("--raw-targets", action="store_true", help="learn the solver's duals as returned")
+    ap.add_argument("--side", type=int, default=SIDE, help="grid side (histograms of side^2 cells)")
     args = ap.parse_args()
     rep = run(args.train, args.test, args.epochs, args.batch, args.lr, args.tol, args.hidden,
-              rho0=args.rho0, data=args.data, canon=not args.raw_targets)
+              rho0=args.rho0, data=args.data, canon=not args.raw_targets, side=args.side)
     print(json.dumps(rep), flush=True)
 
 
