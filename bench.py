@@ -55,7 +55,8 @@ def upload(inst):
     return C, p, q
 
 
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "sweep_f32_4096_pmc.txt")
+def pmc_summary(m, n):
+    return os.path.join(ROOT, "profiles", f"sweep_f32_{m}x{n}_pmc.txt")
 
 
 def pmc_traffic(m, n):
@@ -65,7 +66,7 @@ def pmc_traffic(m, n):
     hash to the values recorded with the counters."""
     import hashlib
     try:
-        lines = open(PMC_SUMMARY).read().splitlines()
+        lines = open(pmc_summary(m, n)).read().splitlines()
     except OSError:
         return None
     kv, hashes = {}, {}
@@ -309,6 +310,32 @@ def time_to_tol(ctx, C, p, q, rho, rho0_name, args, tol=1e-4, max_iter=2_000_000
             "eps_dual": r["eps_dual"], "eps_gap": r["eps_gap"]}
 
 
+def time_to_tol_logged(ctx, C, p, q, rho0, args, tol=1e-4, max_iter=3_000_000, chunk=16384):
+    """time_to_tol for long runs: iterations enqueued in chunks, with a
+    progress line per chunk; the device time comes from the state record
+    (start of initialisation to the iteration that met the test)."""
+    import torch
+    from paper_2110_11738_amd import drot
+    m, n = C.shape
+    rho = rho0 / (m + n)
+    X = torch.empty(C.shape, dtype=C.dtype, device=C.device)
+    ctx.bind(C, p, q, X, drot.make_params(rho, tol, max_iter, check_every=args.check_every))
+    t0 = time.perf_counter()
+    while True:
+        ctx.iterate(chunk)
+        k, stopped = ctx.poll()
+        log(f"  {m}x{n} rho0 {rho0:g}: {k} iterations, {time.perf_counter() - t0:.0f}s")
+        if stopped:
+            break
+    r = ctx.finish()
+    log(f"time to {tol:g} at {m}x{n} (rho0 = {rho0:g}): {r['iters']} iterations, "
+        f"{r['seconds_to_tol']:.2f}s device, status {r['status']}")
+    return {"tol": tol, "rho0": rho0, "rho": rho, "status": r["status"], "iters": r["iters"],
+            "seconds_device": r["seconds_to_tol"], "seconds_host": time.perf_counter() - t0,
+            "objective": r["objective"], "eps_primal": r["eps_primal"],
+            "eps_dual": r["eps_dual"], "eps_gap": r["eps_gap"]}
+
+
 def cpu_baseline(inst, budget_s=20.0):
     """Time the FP64 oracle per iteration on a bounded sample of iterations."""
     import numpy as np
@@ -362,6 +389,11 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-skipc", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuned runs")
+    ap.add_argument("--tol-large", action="store_true",
+                    help="also time the large instance to the 1e-4 test (minutes)")
+    ap.add_argument("--tol-large-rho0", type=float, default=2.0)
+    ap.add_argument("--large-only", action="store_true",
+                    help="skip every section before the large instance (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration for profiles)")
     ap.add_argument("--check-every", type=int, default=64)
@@ -381,92 +413,96 @@ def main():
     drot.lib()
     ctx = drot.Context(0)
 
-    # ---- main workload: 4096^2 float32 -------------------------------------
-    inst = make_instance(args.m, args.n)
-    C, p, q = upload(inst)
-    m, n = args.m, args.n
-    log(f"timing {args.steps} iterations after {args.warmup} warm-up iterations")
-    bind = dense_binder(ctx, C, p, q, inst.rho, args)
-    r = measure(ctx, bind, args.steps, args.warmup)
-    secs, sweep_ms, cnt = r["seconds"], r["sweep_ms"], r["sweeps_timed"]
-    value = args.steps / secs
-    alg_bytes = BYTES_PER_ENTRY_F32 * m * n
-    achieved = alg_bytes / (sweep_ms * 1e-3) / 1e9
-    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "kernel": "sweep_kernel<float,iter>", "bytes_per_launch": alg_bytes,
-            "traffic_bytes_per_launch": None,
-            "avg_launch_us": sweep_ms * 1e3, "launches_timed": cnt,
-            "timing": "hipExtLaunchKernel start/stop events on every sweep of a second timed "
-                      "region (eager launches, same workload and length)",
-            "eager_iter_per_s": args.steps / r["seconds_eager"]}
-    tb = pmc_traffic(m, n)
-    if tb is not None:
-        # Counter bytes per launch over the same average launch duration.
-        roof["traffic"] = tb / (sweep_ms * 1e-3) / 1e9
-        roof["traffic_bytes_per_launch"] = tb
-        roof["traffic_source"] = os.path.relpath(PMC_SUMMARY, ROOT)
-    log(f"{value:.1f} it/s ({1e3 * secs / args.steps:.4f} ms/it); sweep {sweep_ms * 1e3:.2f} us "
-        f"-> {achieved:.0f} GB/s; eager {args.steps / r['seconds_eager']:.1f} it/s")
+    if args.large_only:
+        out = {"metric": "DROT iters/s at 20000^2 (profiling run)", "large_only": True}
+        C = p = q = None
+    else:
+        # ---- main workload: 4096^2 float32 -------------------------------------
+        inst = make_instance(args.m, args.n)
+        C, p, q = upload(inst)
+        m, n = args.m, args.n
+        log(f"timing {args.steps} iterations after {args.warmup} warm-up iterations")
+        bind = dense_binder(ctx, C, p, q, inst.rho, args)
+        r = measure(ctx, bind, args.steps, args.warmup)
+        secs, sweep_ms, cnt = r["seconds"], r["sweep_ms"], r["sweeps_timed"]
+        value = args.steps / secs
+        alg_bytes = BYTES_PER_ENTRY_F32 * m * n
+        achieved = alg_bytes / (sweep_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "sweep_kernel<float,iter>", "bytes_per_launch": alg_bytes,
+                "traffic_bytes_per_launch": None,
+                "avg_launch_us": sweep_ms * 1e3, "launches_timed": cnt,
+                "timing": "hipExtLaunchKernel start/stop events on every sweep of a second timed "
+                          "region (eager launches, same workload and length)",
+                "eager_iter_per_s": args.steps / r["seconds_eager"]}
+        tb = pmc_traffic(m, n)
+        if tb is not None:
+            # Counter bytes per launch over the same average launch duration.
+            roof["traffic"] = tb / (sweep_ms * 1e-3) / 1e9
+            roof["traffic_bytes_per_launch"] = tb
+            roof["traffic_source"] = os.path.relpath(pmc_summary(m, n), ROOT)
+        log(f"{value:.1f} it/s ({1e3 * secs / args.steps:.4f} ms/it); sweep {sweep_ms * 1e3:.2f} us "
+            f"-> {achieved:.0f} GB/s; eager {args.steps / r['seconds_eager']:.1f} it/s")
 
-    out = {
-        "metric": "DROT iters/s + time-to-1e-4 residual at 4096^2 and 20000^2; HBM GB/s vs peak",
-        "value": value, "unit": "iter/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * secs / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": f"DROT mixture2d {m}x{n} float32 (two 2-D 5-Gaussian clouds, "
-                               f"sigma 0.1, sq-Euclidean C / max, Dirichlet(1) marginals, "
-                               f"rho0 = 1/ln m)", "m": m, "n": n, "rho": inst.rho,
-                   "tile_rows": args.tile_rows, "tile_chunks": args.tile_chunks,
-                   "tile_unroll": args.tile_unroll, "cache_mode": args.cache_mode,
-                   "tile_groups": args.tile_groups,
-                   "check_every": args.check_every, "parallelism": "single GPU"},
-        "roofline": roof,
-    }
+        out = {
+            "metric": "DROT iters/s + time-to-1e-4 residual at 4096^2 and 20000^2; HBM GB/s vs peak",
+            "value": value, "unit": "iter/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": 1e3 * secs / args.steps,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": f"DROT mixture2d {m}x{n} float32 (two 2-D 5-Gaussian clouds, "
+                                   f"sigma 0.1, sq-Euclidean C / max, Dirichlet(1) marginals, "
+                                   f"rho0 = 1/ln m)", "m": m, "n": n, "rho": inst.rho,
+                       "tile_rows": args.tile_rows, "tile_chunks": args.tile_chunks,
+                       "tile_unroll": args.tile_unroll, "cache_mode": args.cache_mode,
+                       "tile_groups": args.tile_groups,
+                       "check_every": args.check_every, "parallelism": "single GPU"},
+            "roofline": roof,
+        }
 
-    # ---- the paper's runtime protocol: 10 runs x 100 iterations -----------------
-    out["protocol_10x100"] = protocol_runs(ctx, bind)
-    # ---- a plain device copy on the same box, for scale ---------------------------
-    out["copy_reference"] = copy_reference()
+        # ---- the paper's runtime protocol: 10 runs x 100 iterations -----------------
+        out["protocol_10x100"] = protocol_runs(ctx, bind)
+        # ---- a plain device copy on the same box, for scale ---------------------------
+        out["copy_reference"] = copy_reference()
 
-    if not args.no_tune:
-        tile = tuned_tile(ctx, bind, 256)
-        rt = measure(ctx, dense_binder(ctx, C, p, q, inst.rho, args, tile), args.steps, args.warmup)
-        ach_t = alg_bytes / (rt["sweep_ms"] * 1e-3) / 1e9
-        out["tuned"] = {"tile_rows": tile[0], "tile_chunks": tile[1], "tile_groups": tile[2],
-                        "iter_per_s": args.steps / rt["seconds"],
-                        "avg_launch_us": rt["sweep_ms"] * 1e3, "achieved": ach_t,
-                        "frac": ach_t / HBM_PEAK_GBS}
-        log(f"tuned: {args.steps / rt['seconds']:.1f} it/s, sweep {rt['sweep_ms'] * 1e3:.2f} us "
-            f"-> {ach_t:.0f} GB/s")
+        if not args.no_tune:
+            tile = tuned_tile(ctx, bind, 256)
+            rt = measure(ctx, dense_binder(ctx, C, p, q, inst.rho, args, tile), args.steps, args.warmup)
+            ach_t = alg_bytes / (rt["sweep_ms"] * 1e-3) / 1e9
+            out["tuned"] = {"tile_rows": tile[0], "tile_chunks": tile[1], "tile_groups": tile[2],
+                            "iter_per_s": args.steps / rt["seconds"],
+                            "avg_launch_us": rt["sweep_ms"] * 1e3, "achieved": ach_t,
+                            "frac": ach_t / HBM_PEAK_GBS}
+            log(f"tuned: {args.steps / rt['seconds']:.1f} it/s, sweep {rt['sweep_ms'] * 1e3:.2f} us "
+                f"-> {ach_t:.0f} GB/s")
 
-    # ---- the paper's skip-C schedule on the same workload ---------------------
-    if not args.no_skipc:
-        r = measure(ctx, bind, args.steps, args.warmup, drot.FLAG_SKIP_C)
-        secs_s, sweep_s = r["seconds"], r["sweep_ms"]
-        out["skip_c"] = {"iter_per_s": args.steps / secs_s, "avg_sweep_us": sweep_s * 1e3,
-                         "bytes_per_entry_avg": 10,
-                         "achieved_GBs": 10 * m * n / (sweep_s * 1e-3) / 1e9}
-        log(f"skip-C: {args.steps / secs_s:.1f} it/s, average sweep {sweep_s * 1e3:.2f} us")
+        # ---- the paper's skip-C schedule on the same workload ---------------------
+        if not args.no_skipc:
+            r = measure(ctx, bind, args.steps, args.warmup, drot.FLAG_SKIP_C)
+            secs_s, sweep_s = r["seconds"], r["sweep_ms"]
+            out["skip_c"] = {"iter_per_s": args.steps / secs_s, "avg_sweep_us": sweep_s * 1e3,
+                             "bytes_per_entry_avg": 10,
+                             "achieved_GBs": 10 * m * n / (sweep_s * 1e-3) / 1e9}
+            log(f"skip-C: {args.steps / secs_s:.1f} it/s, average sweep {sweep_s * 1e3:.2f} us")
 
-    # ---- time to the 1e-4 relative stopping test -----------------------------
-    if not args.no_tol:
-        out["time_to_tol"] = time_to_tol(ctx, C, p, q, inst.rho, "1/ln m", args)
-        # the other step-size constant of the paper's experiments
-        rho2 = 2.0 / (m + n)
-        out["time_to_tol_rho0_2"] = time_to_tol(ctx, C, p, q, rho2, "2", args)
+        # ---- time to the 1e-4 relative stopping test -----------------------------
+        if not args.no_tol:
+            out["time_to_tol"] = time_to_tol(ctx, C, p, q, inst.rho, "1/ln m", args)
+            # the other step-size constant of the paper's experiments
+            rho2 = 2.0 / (m + n)
+            out["time_to_tol_rho0_2"] = time_to_tol(ctx, C, p, q, rho2, "2", args)
 
-    # ---- CPU oracle baseline ----------------------------------------------------
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(inst)
-        log(f"cpu oracle {out['cpu_baseline']['value']:.3f} it/s")
+        # ---- CPU oracle baseline ----------------------------------------------------
+        if not args.no_cpu:
+            out["cpu_baseline"] = cpu_baseline(inst)
+            log(f"cpu oracle {out['cpu_baseline']['value']:.3f} it/s")
 
     del C, p, q
     torch.cuda.empty_cache()
-    if not args.no_precision:
+    if not args.no_precision and not args.large_only:
         out["precision"] = precision_section(ctx)
-    if not args.no_batch:
+    if not args.no_batch and not args.large_only:
         out["batch"] = batch_section(ctx)
 
     # ---- 20000^2 roofline instance ----------------------------------------------
@@ -482,10 +518,14 @@ def main():
         r = measure(ctx, binder, ksteps, kwarm)
         secs_l, sweep_l, cnt_l = r["seconds"], r["sweep_ms"], r["sweeps_timed"]
         ach = ab / (sweep_l * 1e-3) / 1e9
+        tb_l = pmc_traffic(L, L)
         out["large"] = {"m": L, "n": L, "iter_per_s": ksteps / secs_l,
                         "ms_per_iter": 1e3 * secs_l / ksteps,
                         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
-                                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                                     "traffic": (tb_l / (sweep_l * 1e-3) / 1e9
+                                                 if tb_l is not None else None),
+                                     "traffic_bytes_per_launch": tb_l,
                                      "bytes_per_launch": ab, "avg_launch_us": sweep_l * 1e3,
                                      "launches_timed": cnt_l}}
         log(f"{L}^2: {ksteps / secs_l:.1f} it/s, sweep {sweep_l * 1e3:.1f} us -> {ach:.0f} GB/s "
@@ -501,6 +541,9 @@ def main():
                                      "frac": ach_t / HBM_PEAK_GBS}
             log(f"{L}^2 tuned: {ksteps / r['seconds']:.1f} it/s, sweep {r['sweep_ms'] * 1e3:.1f} us "
                 f"-> {ach_t:.0f} GB/s ({100 * ach_t / HBM_PEAK_GBS:.1f}% of peak)")
+        if args.tol_large:
+            out["large"]["time_to_tol"] = time_to_tol_logged(ctx, C, p, q, args.tol_large_rho0,
+                                                             args)
 
     if args.calibrate_copy:
         # A plain copy of known size: under `rocprofv3 --pmc FETCH_SIZE` (or
