@@ -227,6 +227,23 @@ __device__ __forceinline__ void block_sum_slots(double (&acc)[kSlots],
 // workgroup loads them when it starts, so that the last workgroup's scalar
 // steps wait on no further load; nothing in them changes during the launch
 // (only the last workgroup writes the state, after all others are done).
+// The value of one of two pointers, chosen by a wave-uniform condition.
+// Each candidate is passed through readfirstlane first, so that the choice is
+// made between values held in registers, never between addresses of
+// argument fields (which would force the arguments into scratch memory).
+template <typename P>
+__device__ __forceinline__ P* pick(bool c, P* x, P* y) {
+  auto uni = [](P* v) {
+    const uint64_t u = reinterpret_cast<uint64_t>(v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return reinterpret_cast<P*>(((uint64_t)hi << 32) | lo);
+  };
+  const P* px = uni(x);
+  const P* py = uni(y);
+  return const_cast<P*>(c ? px : py);
+}
+
 struct StateIn {
   double rho, tol, alpha, sum_p, sum_q, norm_pq, norm_c;
   double cphi, cpsi, sum_phi0, sum_psi0;
@@ -519,99 +536,100 @@ __device__ __forceinline__ void aux_body(const SweepArgs& a, const int b, const 
   __syncthreads();
   if (wave != 0 || (is_iter(MODE) && sv.done)) return;
 
-  // Stage 2 (wave 0): the per-entry steps.
+  // Stage 2 (wave 0): the per-entry steps, written once for both kinds of
+  // workgroup: `tot` is the entry's full sum (u_i or v_j), `len` the length
+  // of the other side (n for rows, m for columns).  The three pointers are
+  // picked as values (made wave-uniform first), so that no field of the
+  // arguments is ever addressed through a runtime choice.
   const double rho = sv.rho;
+  double* const accv = pick(is_col, a.b, a.a);      // a_i or b_j
+  double* const d64 = pick(is_col, a.psi64, a.phi64);
+  T* const dT = static_cast<T*>(pick(is_col, a.psiT, a.phiT));
+  double* const dout = pick(is_col, a.nu_out, a.mu_out);
+  const double len = is_col ? (double)m : (double)n;
+  const double shift = is_col ? sv.cpsi : sv.cphi;
+  const double sum0 = is_col ? sv.sum_phi0 : sv.sum_psi0;
+  // e0, e1, e2: the entry's (residual or a_0 / b_0, its square, marginal x dual)
+  double e0 = 0.0, e1 = 0.0, e2 = 0.0, emarg = 0.0, esq = 0.0, eneg = 0.0, ebad = 0.0;
   if (idx >= 0) {
+    double tot;
     if (is_col) {
-      double v = red2[threadIdx.x];
+      tot = red2[threadIdx.x];
 #pragma unroll
-      for (int g = 1; g < G; ++g) v += red2[g * kAuxCols + threadIdx.x];
-      const int64_t j = idx;
-      const double qj = w0;
-      const double s = v - qj;
-      if (is_iter(MODE)) {
-        const double bj = w1;
-        const double ps = (bj - 2.0 * s) / (double)m;
-        a.b[j] = bj - s;
-        a.psi64[j] = ps;
-        static_cast<T*>(a.psiT)[j] = (T)ps;
-        acc[kSS] = s;
-        acc[kSS2] = s * s;
-        acc[kSQpsi] = qj * ps;
-      } else if (is_final(MODE)) {
-        const double ps = w1 + sv.cpsi;
-        acc[kSS2] = s * s;
-        acc[kSQpsi] = qj * ps;
-        if (a.nu_out) a.nu_out[j] = ps / rho;
-      } else {
-        const double ps0 = rho * w1;
-        const double bj = v - qj + (double)m * ps0 + sv.sum_phi0;
-        a.b[j] = bj;
-        a.psi64[j] = ps0;
-        static_cast<T*>(a.psiT)[j] = (T)ps0;
-        acc[kSS] = bj;
-        acc[kSQ] = qj;
-        acc[kSPQ2] = qj * qj;
-        acc[kSNeg] = qj < 0.0 ? 1.0 : 0.0;
-        acc[kSNonfin] = (!finite_d(qj) || !finite_d(ps0)) ? 1.0 : 0.0;
-      }
+      for (int g = 1; g < G; ++g) tot += red2[g * kAuxCols + threadIdx.x];
     } else {
-      double u = red2[lane];
+      tot = red2[lane];
 #pragma unroll
-      for (int w = 1; w < kWaves; ++w) u += red2[w * kAuxRows + lane];
-      const int64_t i = idx;
-      const double pi = w0;
-      const double r = u - pi;
-      if (is_iter(MODE)) {
-        const double ai = w1;
-        const double ph = (ai - 2.0 * r) / (double)n;
-        a.a[i] = ai - r;
-        a.phi64[i] = ph;
-        static_cast<T*>(a.phiT)[i] = (T)ph;
-        acc[kSR] = r;
-        acc[kSR2] = r * r;
-        acc[kSPphi] = pi * ph;
-      } else if (is_final(MODE)) {
-        const double ph = w1 + sv.cphi;
-        acc[kSR2] = r * r;
-        acc[kSPphi] = pi * ph;
-        if (a.mu_out) a.mu_out[i] = ph / rho;
-      } else {
-        const double ph0 = rho * w1;
-        const double ai = u - pi + (double)n * ph0 + sv.sum_psi0;
-        a.a[i] = ai;
-        a.phi64[i] = ph0;
-        static_cast<T*>(a.phiT)[i] = (T)ph0;
-        acc[kSR] = ai;
-        acc[kSP] = pi;
-        acc[kSPQ2] = pi * pi;
-        acc[kSNeg] = pi < 0.0 ? 1.0 : 0.0;
-        acc[kSNonfin] = (!finite_d(pi) || !finite_d(ph0)) ? 1.0 : 0.0;
-      }
+      for (int w = 1; w < kWaves; ++w) tot += red2[w * kAuxRows + lane];
+    }
+    const double marg = w0;
+    const double res = tot - marg;
+    if (is_iter(MODE)) {
+      const double d = (w1 - 2.0 * res) / len;
+      accv[idx] = w1 - res;
+      d64[idx] = d;
+      dT[idx] = (T)d;
+      e0 = res;
+      e1 = res * res;
+      e2 = marg * d;
+    } else if (is_final(MODE)) {
+      const double d = w1 + shift;
+      e1 = res * res;
+      e2 = marg * d;
+      if (dout) dout[idx] = d / rho;
+    } else {
+      const double d0 = rho * w1;
+      const double acc0 = res + len * d0 + sum0;
+      accv[idx] = acc0;
+      d64[idx] = d0;
+      dT[idx] = (T)d0;
+      e0 = acc0;
+      emarg = marg;
+      esq = marg * marg;
+      eneg = marg < 0.0 ? 1.0 : 0.0;
+      ebad = (!finite_d(marg) || !finite_d(d0)) ? 1.0 : 0.0;
     }
   }
 
   // Publish this workgroup's sums (slot-major), then count it in; the
   // release fence orders the stores before the count and the acquire fence
-  // of the last workgroup orders its loads after it.  In the iteration a
-  // workgroup holds three column (or row) sums and the two tile sums only.
+  // of the last workgroup orders its loads after it.  Column workgroups fill
+  // the column slots, row workgroups the row slots; in the iteration no
+  // other slot is read.
+  double* const bp = a.blockpart + b;
+  const int64_t sb = is_col ? kSS : kSR;  // first of the side's three slots
   unsigned prev = 0;
   if (is_iter(MODE)) {
-    const int s0 = is_col ? kSS : kSR;
-    double w[5] = {is_col ? acc[kSS] : acc[kSR], is_col ? acc[kSS2] : acc[kSR2],
-                   is_col ? acc[kSQpsi] : acc[kSPphi], acc[kST0], acc[kST1]};
+    double w[5] = {e0, e1, e2, acc[kST0], acc[kST1]};
     wave_sum_n(w);
     if (lane == 0) {
-#pragma unroll
-      for (int e = 0; e < 3; ++e) store_agent(a.blockpart + (int64_t)(s0 + e) * nb + b, w[e]);
-      store_agent(a.blockpart + (int64_t)kST0 * nb + b, w[3]);
-      store_agent(a.blockpart + (int64_t)kST1 * nb + b, w[4]);
+      store_agent(bp + (sb + 0) * nb, w[0]);
+      store_agent(bp + (sb + 1) * nb, w[1]);
+      store_agent(bp + (sb + 2) * nb, w[2]);
+      store_agent(bp + (int64_t)kST0 * nb, w[3]);
+      store_agent(bp + (int64_t)kST1 * nb, w[4]);
     }
   } else {
-    wave_sum_n(acc);
+    // Initialisation / final evaluation: all 13 slots, zeros included.
+    double w[10] = {e0, e1, e2, emarg, esq, eneg, ebad, acc[kST0], acc[kST1], 0.0};
+    wave_sum_n(w);
+    const double r0 = is_col ? 0.0 : w[0], r1 = is_col ? 0.0 : w[1], r2 = is_col ? 0.0 : w[2];
+    const double c0 = is_col ? w[0] : 0.0, c1 = is_col ? w[1] : 0.0, c2 = is_col ? w[2] : 0.0;
+    const double sp = is_col ? 0.0 : w[3], sq = is_col ? w[3] : 0.0;
     if (lane == 0) {
-#pragma unroll
-      for (int s = 0; s < kSlots; ++s) store_agent(a.blockpart + (int64_t)s * nb + b, acc[s]);
+      store_agent(bp + (int64_t)kSR * nb, r0);
+      store_agent(bp + (int64_t)kSR2 * nb, r1);
+      store_agent(bp + (int64_t)kSPphi * nb, r2);
+      store_agent(bp + (int64_t)kSS * nb, c0);
+      store_agent(bp + (int64_t)kSS2 * nb, c1);
+      store_agent(bp + (int64_t)kSQpsi * nb, c2);
+      store_agent(bp + (int64_t)kST0 * nb, w[7]);
+      store_agent(bp + (int64_t)kST1 * nb, w[8]);
+      store_agent(bp + (int64_t)kSP * nb, sp);
+      store_agent(bp + (int64_t)kSQ * nb, sq);
+      store_agent(bp + (int64_t)kSPQ2 * nb, w[4]);
+      store_agent(bp + (int64_t)kSNeg * nb, w[5]);
+      store_agent(bp + (int64_t)kSNonfin * nb, w[6]);
     }
   }
   if (lane == 0) {
@@ -636,7 +654,9 @@ template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void aux_batch_kernel(const SweepArgs* __restrict__ args,
                                                            const uint2* __restrict__ work) {
   const uint2 w = work[blockIdx.x];
-  const SweepArgs& a = args[w.x];
+  // A private copy of the problem's arguments: read through the pointer,
+  // every field would be reloaded after each store the kernel makes.
+  const SweepArgs a = args[__builtin_amdgcn_readfirstlane(w.x)];
   aux_body<T, MODE>(a, (int)w.y, (int)aux_workgroups(a.g.m, a.g.n));
 }
 
@@ -927,7 +947,7 @@ template <typename T, int MODE, int VEC, int CH, bool NT, bool RAGGED>
 __global__ __launch_bounds__(kBlock) void sweep_batch_kernel(const SweepArgs* __restrict__ args,
                                                              const uint2* __restrict__ work) {
   const uint2 w = work[blockIdx.x];
-  const SweepArgs& a = args[w.x];
+  const SweepArgs a = args[__builtin_amdgcn_readfirstlane(w.x)];  // private copy, as above
   sweep_body<T, MODE, VEC, CH, 4, NT, kCostDense, 1, RAGGED>(a, (int)(w.y % a.g.n_ct),
                                                               (int)(w.y / a.g.n_ct));
 }
@@ -962,7 +982,8 @@ __device__ __forceinline__ void prep_body(const SweepArgs& a) {
 __global__ __launch_bounds__(kBlock) void prep_kernel(SweepArgs a) { prep_body(a); }
 
 __global__ __launch_bounds__(kBlock) void prep_batch_kernel(const SweepArgs* __restrict__ args) {
-  prep_body(args[blockIdx.x]);
+  const SweepArgs a = args[blockIdx.x];
+  prep_body(a);
 }
 
 // Stream of a sweep launch, with optional events that hipExtLaunchKernel
