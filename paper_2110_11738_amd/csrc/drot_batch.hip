@@ -239,7 +239,7 @@ extern "C" int drot_solve_batched(drot_ctx* c, int32_t count, int dtype, const d
     BHIP(hipMemcpyAsync(d_sw, h_sw, sizeof(uint2) * n_sw, hipMemcpyHostToDevice, s));
     BHIP(hipMemcpyAsync(d_aw, h_aw, sizeof(uint2) * n_aw, hipMemcpyHostToDevice, s));
     BHIP(launch_prep_batch(d_args, count, s));
-    BHIP(launch_batch_step(dtype, kInitPQ, tile, d_args, d_sw, n_sw, d_aw, n_aw, s));
+    BHIP(launch_batch_step(dtype, kInitPQ, tile, d_args, d_sw, n_sw, d_aw, n_aw, count, s));
     BHIP(hipMemcpyAsync(h_st, base, SS * count, hipMemcpyDeviceToHost, s));
     BHIP(hipStreamSynchronize(s));
     const double eps = dtype == DROT_F32 ? 1.1920929e-07 : 2.220446049250313e-16;
@@ -270,7 +270,7 @@ extern "C" int drot_solve_batched(drot_ctx* c, int32_t count, int dtype, const d
           BHIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
           hipError_t le = hipSuccess;
           for (int k = 0; k < G && le == hipSuccess; ++k)
-            le = launch_batch_step(dtype, kIter, tile, d_args, d_sw, n_sw, d_aw, n_aw, cap);
+            le = launch_batch_step(dtype, kIter, tile, d_args, d_sw, n_sw, d_aw, n_aw, count, cap);
           hipError_t ee = hipStreamEndCapture(cap, &graph);
           if (le != hipSuccess || ee != hipSuccess) {
             if (graph) (void)hipGraphDestroy(graph);
@@ -294,7 +294,7 @@ extern "C" int drot_solve_batched(drot_ctx* c, int32_t count, int dtype, const d
         BHIP(hipMemcpyAsync(d_sw, h_sw, sizeof(uint2) * n_sw, hipMemcpyHostToDevice, s));
         BHIP(hipMemcpyAsync(d_aw, h_aw, sizeof(uint2) * n_aw, hipMemcpyHostToDevice, s));
         for (int k = 0; k < G; ++k)
-          BHIP(launch_batch_step(dtype, kIter, tile, d_args, d_sw, n_sw, d_aw, n_aw, s));
+          BHIP(launch_batch_step(dtype, kIter, tile, d_args, d_sw, n_sw, d_aw, n_aw, count, s));
       }
       BHIP(hipMemcpyAsync(h_st, base, SS * count, hipMemcpyDeviceToHost, s));
       BHIP(hipStreamSynchronize(s));
@@ -319,7 +319,7 @@ extern "C" int drot_solve_batched(drot_ctx* c, int32_t count, int dtype, const d
     build_lists(true);
     BHIP(hipMemcpyAsync(d_sw, h_sw, sizeof(uint2) * n_sw, hipMemcpyHostToDevice, s));
     BHIP(hipMemcpyAsync(d_aw, h_aw, sizeof(uint2) * n_aw, hipMemcpyHostToDevice, s));
-    BHIP(launch_batch_step(dtype, kFinal, tile, d_args, d_sw, n_sw, d_aw, n_aw, s));
+    BHIP(launch_batch_step(dtype, kFinal, tile, d_args, d_sw, n_sw, d_aw, n_aw, count, s));
     BHIP(hipMemcpyAsync(h_st, base, SS * count, hipMemcpyDeviceToHost, s));
     BHIP(hipStreamSynchronize(s));
   }

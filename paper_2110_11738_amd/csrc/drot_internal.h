@@ -16,6 +16,7 @@ constexpr int kTraceCap = 65536;   // per-iteration records kept on the device
 constexpr int kTraceWidth = 8;
 constexpr int kAuxCols = 64;       // columns per aux column workgroup
 constexpr int kAuxRows = kWave;    // rows per aux row workgroup
+constexpr int kAuxSplitMin = 256;  // from this many aux workgroups: separate finishing launch
 
 // Workgroups of one aux launch: column groups of kAuxCols, then row groups of
 // kAuxRows.
@@ -161,7 +162,7 @@ hipError_t launch_maxc(const SweepArgs& a, hipStream_t s);
 // one iteration (dense cost, 4 rows in flight).
 hipError_t launch_batch_step(int dtype, int mode, const TileCfg& t, const SweepArgs* args,
                              const uint2* sweep_work, int64_t n_sweep, const uint2* aux_work,
-                             int64_t n_aux, hipStream_t s);
+                             int64_t n_aux, int n_prob, hipStream_t s);
 hipError_t launch_prep_batch(const SweepArgs* args, int count, hipStream_t s);
 
 }  // namespace drot

@@ -448,7 +448,7 @@ __device__ __forceinline__ void sum_strided(const V* base, int64_t stride, int r
 // last-workgroup election; the other waves leave after the loads.  Wave 0 of
 // the last workgroup does the scalar steps.
 // ---------------------------------------------------------------------------
-template <typename T, int MODE, bool WIDE = false>
+template <typename T, int MODE, bool WIDE = false, bool SPLIT = false>
 __device__ __forceinline__ void aux_body(const SweepArgs& a, const int b, const int nb) {
   using P = typename std::conditional<WIDE, double, typename PartialOf<T, MODE>::type>::type;
   constexpr int CW = 16 / sizeof(P);      // columns per 16-byte chunk
@@ -632,6 +632,9 @@ __device__ __forceinline__ void aux_body(const SweepArgs& a, const int b, const 
       store_agent(bp + (int64_t)kSNonfin * nb, w[6]);
     }
   }
+  // Split form: the scalar steps run in a separate one-workgroup launch, and
+  // the kernel boundary publishes the sums (no fence per workgroup).
+  if constexpr (SPLIT) return;
   if (lane == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     prev = __hip_atomic_fetch_add(&a.st->counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -644,9 +647,31 @@ __device__ __forceinline__ void aux_body(const SweepArgs& a, const int b, const 
     __hip_atomic_store(&a.st->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <typename T, int MODE, bool WIDE = false>
+template <typename T, int MODE, bool WIDE = false, bool SPLIT = false>
 __global__ __launch_bounds__(kBlock) void aux_kernel(SweepArgs a) {
-  aux_body<T, MODE, WIDE>(a, blockIdx.x, gridDim.x);
+  aux_body<T, MODE, WIDE, SPLIT>(a, blockIdx.x, gridDim.x);
+}
+
+// The scalar steps after a split aux launch: one wave.
+template <int MODE>
+__device__ __forceinline__ void finish_body(const SweepArgs& a) {
+  const StateIn sv = load_state(a.st);
+  if (is_iter(MODE) && sv.done) return;
+  const int nb = (int)aux_workgroups(a.g.m, a.g.n);
+  const int col_wgs = (int)((a.g.n + kAuxCols - 1) / kAuxCols);
+  finish_global<MODE>(a, sv, nb, col_wgs);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kWave) void finish_kernel(SweepArgs a) {
+  finish_body<MODE>(a);
+}
+
+// Batched form: one wave per problem (finished problems return at once).
+template <int MODE>
+__global__ __launch_bounds__(kWave) void finish_batch_kernel(const SweepArgs* __restrict__ args) {
+  const SweepArgs a = args[blockIdx.x];
+  finish_body<MODE>(a);
 }
 
 // Batched form: work item = (problem, aux workgroup of that problem).
@@ -657,7 +682,7 @@ __global__ __launch_bounds__(kBlock) void aux_batch_kernel(const SweepArgs* __re
   // A private copy of the problem's arguments: read through the pointer,
   // every field would be reloaded after each store the kernel makes.
   const SweepArgs a = args[__builtin_amdgcn_readfirstlane(w.x)];
-  aux_body<T, MODE>(a, (int)w.y, (int)aux_workgroups(a.g.m, a.g.n));
+  aux_body<T, MODE, false, true>(a, (int)w.y, (int)aux_workgroups(a.g.m, a.g.n));
 }
 
 // Per-lane accumulator of the sweep.  Plain: a running sum in the partial
@@ -1170,26 +1195,40 @@ __global__ __launch_bounds__(kBlock) void maxc_kernel(SweepArgs a) {
   if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(&a.st->maxc_bits, __float_as_uint(mx));
 }
 
+// One aux launch in the form chosen by the workgroup count: with many
+// workgroups the last-arriving election costs one L2 write-back per workgroup
+// (its release fence), so above kAuxSplitMin workgroups the aux kernel only
+// publishes its sums and a one-wave kernel does the scalar steps.
+template <typename T, int MODE, bool WIDE>
+hipError_t aux_go(const SweepArgs& a, hipStream_t s) {
+  const int64_t nb = aux_workgroups(a.g.m, a.g.n);
+  const dim3 grid((unsigned)nb);
+  if (nb >= kAuxSplitMin) {
+    hipLaunchKernelGGL((aux_kernel<T, MODE, WIDE, true>), grid, dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((finish_kernel<MODE>), dim3(1), dim3(kWave), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((aux_kernel<T, MODE, WIDE, false>), grid, dim3(kBlock), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t aux_type(int mode, bool wide, const SweepArgs& a, hipStream_t s) {
-  const dim3 grid((unsigned)aux_workgroups(a.g.m, a.g.n));
   if (wide && std::is_same<T, float>::value) {
     // Float64 partials of the compensated float32 iteration.
     if (mode != kIter) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((aux_kernel<T, kIter, true>), grid, dim3(kBlock), 0, s, a);
-    return hipGetLastError();
+    return aux_go<T, kIter, true>(a, s);
   }
   switch (mode) {
     case kIter:
-    case kIterA: hipLaunchKernelGGL((aux_kernel<T, kIter>), grid, dim3(kBlock), 0, s, a); break;
-    case kIterB: hipLaunchKernelGGL((aux_kernel<T, kIterB>), grid, dim3(kBlock), 0, s, a); break;
+    case kIterA: return aux_go<T, kIter, false>(a, s);
+    case kIterB: return aux_go<T, kIterB, false>(a, s);
     case kInitPQ:
-    case kInitX: hipLaunchKernelGGL((aux_kernel<T, kInitPQ>), grid, dim3(kBlock), 0, s, a); break;
+    case kInitX: return aux_go<T, kInitPQ, false>(a, s);
     case kFinal:
-    case kFinalW: hipLaunchKernelGGL((aux_kernel<T, kFinal>), grid, dim3(kBlock), 0, s, a); break;
-    default: return hipErrorInvalidValue;
+    case kFinalW: return aux_go<T, kFinal, false>(a, s);
   }
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -1225,25 +1264,36 @@ hipError_t sweep_batch_mode(const TileCfg& t, const SweepArgs* args, const uint2
   return hipGetLastError();
 }
 
+// Batched aux: every workgroup publishes its sums, then one wave per problem
+// does the scalar steps (a per-workgroup release fence would cost one L2
+// write-back per workgroup of every problem).
+template <typename T, int MODE>
+void batch_aux(const SweepArgs* args, const uint2* aux_work, int64_t n_aux, int n_prob,
+               hipStream_t s) {
+  hipLaunchKernelGGL((aux_batch_kernel<T, MODE>), dim3((unsigned)n_aux), dim3(kBlock), 0, s, args,
+                     aux_work);
+  hipLaunchKernelGGL((finish_batch_kernel<MODE>), dim3((unsigned)n_prob), dim3(kWave), 0, s, args);
+}
+
 template <typename T>
 hipError_t batch_type(int mode, const TileCfg& t, const SweepArgs* args, const uint2* sweep_work,
-                      int64_t n_sweep, const uint2* aux_work, int64_t n_aux, hipStream_t s) {
+                      int64_t n_sweep, const uint2* aux_work, int64_t n_aux, int n_prob,
+                      hipStream_t s) {
   hipError_t e = hipSuccess;
-  const dim3 ag((unsigned)n_aux), block(kBlock);
   switch (mode) {
     case kIter:
       e = sweep_batch_mode<T, kIter>(t, args, sweep_work, n_sweep, s);
-      if (e == hipSuccess) hipLaunchKernelGGL((aux_batch_kernel<T, kIter>), ag, block, 0, s, args, aux_work);
+      if (e == hipSuccess) batch_aux<T, kIter>(args, aux_work, n_aux, n_prob, s);
       break;
     case kInitPQ:
     case kInitX:
       e = mode == kInitPQ ? sweep_batch_mode<T, kInitPQ>(t, args, sweep_work, n_sweep, s)
                           : sweep_batch_mode<T, kInitX>(t, args, sweep_work, n_sweep, s);
-      if (e == hipSuccess) hipLaunchKernelGGL((aux_batch_kernel<T, kInitPQ>), ag, block, 0, s, args, aux_work);
+      if (e == hipSuccess) batch_aux<T, kInitPQ>(args, aux_work, n_aux, n_prob, s);
       break;
     case kFinal:
       e = sweep_batch_mode<T, kFinal>(t, args, sweep_work, n_sweep, s);
-      if (e == hipSuccess) hipLaunchKernelGGL((aux_batch_kernel<T, kFinal>), ag, block, 0, s, args, aux_work);
+      if (e == hipSuccess) batch_aux<T, kFinal>(args, aux_work, n_aux, n_prob, s);
       break;
     default: return hipErrorInvalidValue;
   }
@@ -1254,10 +1304,11 @@ hipError_t batch_type(int mode, const TileCfg& t, const SweepArgs* args, const u
 
 hipError_t launch_batch_step(int dtype, int mode, const TileCfg& t, const SweepArgs* args,
                              const uint2* sweep_work, int64_t n_sweep, const uint2* aux_work,
-                             int64_t n_aux, hipStream_t s) {
+                             int64_t n_aux, int n_prob, hipStream_t s) {
   if (n_sweep <= 0 || n_aux <= 0) return hipSuccess;
-  return dtype == 0 ? batch_type<float>(mode, t, args, sweep_work, n_sweep, aux_work, n_aux, s)
-                    : batch_type<double>(mode, t, args, sweep_work, n_sweep, aux_work, n_aux, s);
+  return dtype == 0
+             ? batch_type<float>(mode, t, args, sweep_work, n_sweep, aux_work, n_aux, n_prob, s)
+             : batch_type<double>(mode, t, args, sweep_work, n_sweep, aux_work, n_aux, n_prob, s);
 }
 
 hipError_t launch_prep_batch(const SweepArgs* args, int count, hipStream_t s) {
