@@ -61,7 +61,10 @@ def _rel_max(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
-SHAPES = [(1, 1), (1, 7), (9, 1), (3, 5), (37, 129), (300, 260), (513, 1030), (64, 2048)]
+# The last two shapes need 257 aux workgroups, which takes the split aux form
+# (publish-only aux launch plus a separate finishing launch).
+SHAPES = [(1, 1), (1, 7), (9, 1), (3, 5), (37, 129), (300, 260), (513, 1030), (64, 2048),
+          (16384, 64), (64, 16384)]
 
 
 @pytest.mark.parametrize("dtype", ["float64", "float32"])
