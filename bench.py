@@ -336,6 +336,104 @@ def time_to_tol_logged(ctx, C, p, q, rho0, args, tol=1e-4, max_iter=3_000_000, c
             "eps_dual": r["eps_dual"], "eps_gap": r["eps_gap"]}
 
 
+def run_to_tol(ctx, bind, label, tol=1e-4, max_iter=3_000_000, chunk=8192):
+    """Bind (bind(flags, max_iter) with the tolerance set by the binder), then
+    iterate in chunks with a progress line per chunk until the device stop
+    flag is set; returns the final result record."""
+    bind(0, max_iter)
+    t0 = time.perf_counter()
+    while True:
+        ctx.iterate(chunk)
+        k, stopped = ctx.poll()
+        if stopped:
+            break
+        log(f"  {label}: {k} iterations, {time.perf_counter() - t0:.0f}s")
+    r = ctx.finish()
+    log(f"{label}: {r['iters']} iterations, {r['seconds_to_tol']:.2f}s device to {tol:g}, "
+        f"status {r['status']}, objective {r['objective']:.8e}")
+    return {"iters": r["iters"], "seconds_device": r["seconds_to_tol"], "status": r["status"],
+            "objective": r["objective"], "eps_primal": r["eps_primal"], "eps_dual": r["eps_dual"],
+            "eps_gap": r["eps_gap"]}
+
+
+def tol_forms_section(ctx, rho0=2.0, tol=1e-4, n_seq=64):
+    """Time to the 1e-4 relative test of the plain float32 form against the
+    reduced-byte forms (10000 x 15000) and the batched form (512 ragged
+    problems; the one-by-one comparison on the first n_seq of them)."""
+    import numpy as np
+    import torch
+    from gen import config_batch, config_cube_3d
+    from paper_2110_11738_amd import drot
+    out = {"tol": tol, "rho0": rho0}
+    inst = config_cube_3d(0)
+    m, n = inst.m, inst.n
+    rho = rho0 / (m + n)
+    C32 = torch.from_numpy(inst.C.astype(np.float32)).cuda()
+    Cb = C32.to(torch.bfloat16)
+    xs = torch.from_numpy(inst.xs.astype(np.float32)).cuda()
+    xt = torch.from_numpy(inst.xt.astype(np.float32)).cuda()
+    p = torch.from_numpy(inst.p.astype(np.float32)).cuda()
+    q = torch.from_numpy(inst.q.astype(np.float32)).cuda()
+    scale = float(inst.cscale)
+    del inst
+    X = torch.empty((m, n), dtype=torch.float32, device="cuda")
+    forms = {}
+    for name, kind, keep, fl in (("dense_f32", drot.COST_DENSE, (C32,), 0),
+                                 ("dense_f32_compensated", drot.COST_DENSE, (C32,),
+                                  drot.FLAG_COMPENSATED),
+                                 ("bf16", drot.COST_BF16, (Cb,), 0),
+                                 ("coords", drot.COST_COORDS, (xs, xt), 0)):
+        cost = drot.make_cost(kind, C=C32 if kind == drot.COST_DENSE else Cb, xs=xs, xt=xt,
+                              scale=scale)
+
+        def bind(flags, max_iter, cost=cost, keep=keep, fl=fl):
+            prm = drot.make_params(rho, tol, max_iter, check_every=64, flags=flags | fl)
+            ctx.bind_cost(m, n, cost, p, q, X, prm, keep=keep)
+        forms[name] = run_to_tol(ctx, bind, f"{m}x{n} {name}", tol)
+    out["precision_10000x15000"] = forms
+    del C32, Cb, xs, xt, X
+    torch.cuda.empty_cache()
+    # batched vs one by one
+    insts = config_batch(512)
+    probs = []
+    for I in insts:
+        probs.append({"C": drot.padded(torch.from_numpy(I.C.astype(np.float32)).cuda()),
+                      "p": torch.from_numpy(I.p.astype(np.float32)).cuda(),
+                      "q": torch.from_numpy(I.q.astype(np.float32)).cuda(),
+                      "rho": rho0 / (I.m + I.n), "tol": tol})
+    del insts
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, outs = drot.solve_batched(probs[:n_seq], max_iter=3_000_000, check_every=64, ctx=ctx)
+    torch.cuda.synchronize()
+    t_b_sub = time.perf_counter() - t0
+    it_sub = [o[1]["iters"] for o in outs]
+    del outs
+    log(f"batched {n_seq} to {tol:g}: {t_b_sub:.2f}s (iterations {min(it_sub)}..{max(it_sub)})")
+    t0 = time.perf_counter()
+    for k, pr in enumerate(probs[:n_seq]):
+        drot.solve(pr["C"], pr["p"], pr["q"], pr["rho"], tol=tol, max_iter=3_000_000,
+                   check_every=64, ctx=ctx)
+        if k % 16 == 15:
+            log(f"  one by one: {k + 1}/{n_seq}, {time.perf_counter() - t0:.0f}s")
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rc, outs = drot.solve_batched(probs, max_iter=3_000_000, check_every=64, ctx=ctx)
+    torch.cuda.synchronize()
+    t_b_all = time.perf_counter() - t0
+    its = [o[1]["iters"] for o in outs]
+    n_conv = sum(1 for o in outs if o[1]["status"] == 0)
+    del outs
+    log(f"batched 512 to {tol:g}: {t_b_all:.2f}s ({n_conv} converged, iterations "
+        f"{min(its)}..{max(its)}); first {n_seq}: batched {t_b_sub:.2f}s vs one by one {t_seq:.2f}s")
+    out["batch"] = {"problems": len(probs), "seconds_batched_all": t_b_all, "converged": n_conv,
+                    "iters_min": min(its), "iters_max": max(its),
+                    "iters_mean": float(np.mean(its)), "subset": n_seq,
+                    "seconds_batched_subset": t_b_sub, "seconds_one_by_one_subset": t_seq}
+    return out
+
+
 def cpu_baseline(inst, budget_s=20.0):
     """Time the FP64 oracle per iteration on a bounded sample of iterations."""
     import numpy as np
@@ -392,6 +490,10 @@ def main():
     ap.add_argument("--tol-large", action="store_true",
                     help="also time the large instance to the 1e-4 test (minutes)")
     ap.add_argument("--tol-large-rho0", type=float, default=2.0)
+    ap.add_argument("--tol-forms", action="store_true",
+                    help="time to 1e-4 of the reduced-byte and batched forms against plain float32 "
+                         "(minutes)")
+    ap.add_argument("--tol-forms-rho0", type=float, default=2.0)
     ap.add_argument("--large-only", action="store_true",
                     help="skip every section before the large instance (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -544,6 +646,9 @@ def main():
         if args.tol_large:
             out["large"]["time_to_tol"] = time_to_tol_logged(ctx, C, p, q, args.tol_large_rho0,
                                                              args)
+
+    if args.tol_forms:
+        out["time_to_tol_forms"] = tol_forms_section(ctx, rho0=args.tol_forms_rho0)
 
     if args.calibrate_copy:
         # A plain copy of known size: under `rocprofv3 --pmc FETCH_SIZE` (or
