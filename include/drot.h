@@ -38,6 +38,7 @@
 #ifndef DROT_H
 #define DROT_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -125,7 +126,8 @@ typedef struct {
   int32_t tile_chunks; /* 16-byte column chunks per lane (1 or 2) */
   int32_t tile_unroll; /* rows whose loads a wave keeps in flight (4 or 8) */
   int32_t cache_mode;  /* drot_cache_mode for the plan and cost streams */
-  int32_t tile_groups; /* row groups (workgroups per strip) */
+  int32_t tile_groups; /* row groups (workgroups per strip); 0 = one row block per
+                          workgroup when cached, two when streaming */
   int32_t reserved;    /* must be 0 */
 } drot_params;
 
@@ -281,8 +283,9 @@ typedef struct {
 } drot_problem;
 
 /* Solve `count` independent problems of any shapes together: every iteration
- * is one batched sweep and one batched aux launch over the (problem, tile)
- * work items of the problems still running, replayed as hipGraphs of
+ * is one batched sweep launch, one batched aux launch over the (problem, tile)
+ * work items of the problems still running and one finishing launch (one
+ * wave per problem), replayed as hipGraphs of
  * params->check_every iterations.  Each problem runs Algorithm 1 with its own
  * stopping test and stops on its own; finished problems leave the work lists
  * when they make up half of them.  params supplies max_iter, tol_mode,
