@@ -502,8 +502,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the DROT sweep of this build runs on a single "
-              "MI355X (multi-GPU row sharding is a design note, not built). Use --gpus 1.",
+        print("bench.py measures one GPU only: the library runs each problem on a single "
+              "MI355X (sharding rows across GPUs is not implemented). Use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 

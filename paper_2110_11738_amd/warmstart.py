@@ -2,8 +2,8 @@
 
 A network maps the marginals (p, q) of a problem on a 32 x 32 grid to initial
 dual variables (mu, nu); DROT then starts from phi_0 = rho mu, psi_0 = rho nu
-(valid from any start by Lemma 1), and cold DROT remains the fallback and the
-judge of the final error.  Everything numerical runs on the GPU through
+(valid from any start by Lemma 1); cold DROT remains the fallback, and the
+warm-started run meets the same stopping test.  Everything numerical runs on the GPU through
 libdrot.so: the training targets come from DROT itself (batched solver), and
 the network is trained and evaluated with the library's MLP kernels.
 
