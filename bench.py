@@ -290,13 +290,13 @@ def copy_reference(mib=256, reps=20):
     return {"bytes_moved": 2 * (mib << 20), "us": ms * 1e3, "GBs": gbs}
 
 
-def time_to_tol(ctx, C, p, q, rho, rho0_name, args, tol=1e-4, max_iter=2_000_000):
+def time_to_tol(ctx, C, p, q, rho, rho0_name, args, tol=1e-4, max_iter=2_000_000, flags=0):
     """Solve to the relative tolerance; device seconds from the start of the
     initialisation to the iteration that met the test."""
     import torch
     from paper_2110_11738_amd import drot
     X = torch.empty(C.shape, dtype=C.dtype, device=C.device)
-    prm = drot.make_params(rho, tol, max_iter, check_every=args.check_every,
+    prm = drot.make_params(rho, tol, max_iter, check_every=args.check_every, flags=flags,
                            tile_rows=args.tile_rows, tile_chunks=args.tile_chunks,
                            tile_unroll=args.tile_unroll, cache_mode=args.cache_mode,
                            tile_groups=args.tile_groups)
@@ -594,6 +594,9 @@ def main():
             # the other step-size constant of the paper's experiments
             rho2 = 2.0 / (m + n)
             out["time_to_tol_rho0_2"] = time_to_tol(ctx, C, p, q, rho2, "2", args)
+            # the paper's skip-C schedule (Claim 1), same problem and step size
+            out["time_to_tol_skip_c"] = time_to_tol(ctx, C, p, q, inst.rho, "1/ln m, skip-C", args,
+                                                    flags=drot.FLAG_SKIP_C)
 
         # ---- CPU oracle baseline ----------------------------------------------------
         if not args.no_cpu:
