@@ -59,12 +59,25 @@ def pmc_summary(m, n):
     return os.path.join(ROOT, "profiles", f"sweep_f32_{m}x{n}_pmc.txt")
 
 
+def source_digest(path):
+    """sha256 of a C/HIP source with its comments and blank lines removed, so
+    that the recorded counters stay attached to the code they measured and
+    survive edits of comments only."""
+    import hashlib
+    import re
+    with open(path, encoding="utf-8") as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    lines = [ln.rstrip() for ln in text.splitlines() if ln.strip()]
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()
+
+
 def pmc_traffic(m, n):
     """HBM bytes per sweep launch measured with rocprofv3 FETCH_SIZE and
     WRITE_SIZE (scaled by a plain copy of known size), read from the profile
     summary; None unless it covers this workload and the kernel sources still
-    hash to the values recorded with the counters."""
-    import hashlib
+    have the code digests (source_digest) recorded with the counters."""
     try:
         lines = open(pmc_summary(m, n)).read().splitlines()
     except OSError:
@@ -74,7 +87,7 @@ def pmc_traffic(m, n):
         if not line or line.startswith("#"):
             continue
         parts = line.split()
-        if parts[0] == "source_sha256" and len(parts) == 3:
+        if parts[0] == "source_digest" and len(parts) == 3:
             hashes[parts[1]] = parts[2]
         else:
             kv[parts[0]] = " ".join(parts[1:])
@@ -82,9 +95,8 @@ def pmc_traffic(m, n):
         return None
     for rel, h in hashes.items():
         try:
-            with open(os.path.join(ROOT, rel), "rb") as fh:
-                if hashlib.sha256(fh.read()).hexdigest() != h:
-                    return None
+            if source_digest(os.path.join(ROOT, rel)) != h:
+                return None
         except OSError:
             return None
     return float(kv["sweep_traffic_bytes"])

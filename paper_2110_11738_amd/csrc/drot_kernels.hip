@@ -17,7 +17,9 @@
 //                the workgroups' scalar partials in a fixed order and does the
 //                scalar steps: beta = f^T r/(m+n), the common scalar part
 //                (2 beta - alpha) of the new shifts, alpha <- alpha - beta,
-//                and the stopping test.
+//                and the stopping test.  With many aux workgroups (and in the
+//                batched solver) a separate one-wave finish_kernel does these
+//                scalar steps instead, after the aux launch.
 //
 // The shifts are kept as phi = phi~ + (2 beta - alpha)/n and
 // psi = psi~ + (2 beta - alpha)/m (the algebra of steps 6-7): the vector parts
@@ -25,7 +27,8 @@
 // row shift, so no second pass over the vectors is needed once beta is known.
 //
 // Every sum runs in a fixed order, so results are bit-reproducible; the only
-// atomics are the integer counter that elects the last aux workgroup.
+// atomics are the integer counter that elects the last aux workgroup and the
+// maximum of the coordinates cost (order-independent).
 //
 // Differences from the paper's CUDA kernel (Section 3, "Main kernel"): that
 // kernel is column-major with one thread per row and sums columns with float
