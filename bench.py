@@ -281,6 +281,71 @@ def protocol_runs(ctx, bind, runs=10, iters=100):
             "interval_iter_per_s": [lo, hi], "interval": "order statistics 2 and 9 of 10"}
 
 
+def paper_sizes_section(ctx, sizes=(100, 200, 500, 1000, 2000, 5000, 10000, 20000), runs=10,
+                        iters=100):
+    """The paper's runtime experiment: m = n from 100 to 20000, its 2-D
+    Gaussian generator (sigma_t = 5, uniform marginals), rho0 = 1/ln m; per
+    size `runs` runs of `iters` iterations from a fresh bind, median
+    iterations/s and the interval of order statistics 2 and 9."""
+    import math
+    import statistics
+    import numpy as np
+    import torch
+    from gen import paper_protocol
+    from paper_2110_11738_amd import drot
+    out = []
+    for m in sizes:
+        inst = paper_protocol(0, m, rho0=1.0 / math.log(m))
+        C = torch.from_numpy(inst.C.astype(np.float32)).cuda()
+        p = torch.from_numpy(inst.p.astype(np.float32)).cuda()
+        q = torch.from_numpy(inst.q.astype(np.float32)).cuda()
+        X = torch.empty_like(C)
+        rho = inst.rho
+        del inst
+        rates = []
+        for _ in range(runs):
+            ctx.bind(C, p, q, X, drot.make_params(rho, 0.0, iters + 1, check_every=iters))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.iterate(iters)
+            torch.cuda.synchronize()
+            rates.append(iters / (time.perf_counter() - t0))
+        r = sorted(rates)
+        lo, hi = (r[1], r[-2]) if runs >= 10 else (r[0], r[-1])
+        med = statistics.median(r)
+        gbs = 12.0 * m * m * med / 1e9
+        log(f"paper sizes {m}x{m}: median {med:.1f} it/s [{lo:.1f}, {hi:.1f}], {gbs:.0f} GB/s")
+        out.append({"m": m, "n": m, "median_iter_per_s": med, "interval": [lo, hi],
+                    "ms_per_iter": 1e3 / med, "algorithmic_GBs": gbs})
+        del C, p, q, X
+        torch.cuda.empty_cache()
+    return out
+
+
+def phase_times(ctx, bind, reps=5):
+    """Host wall time of the phases around the iteration: bind (validation,
+    initialisation pass X_0 = p q^T with its sums, and the check of the
+    marginals, which waits for the device) and the final FP64 evaluation pass
+    (drot_finish); median of `reps`."""
+    import statistics
+    import torch
+    b, f = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bind(0, 10)
+        b.append(1e3 * (time.perf_counter() - t0))
+        ctx.iterate(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.finish()
+        f.append(1e3 * (time.perf_counter() - t0))
+    res = {"bind_with_init_pass": statistics.median(b), "final_evaluation": statistics.median(f)}
+    log(f"phases: bind + initialisation {res['bind_with_init_pass']:.3f} ms, final evaluation "
+        f"{res['final_evaluation']:.3f} ms")
+    return res
+
+
 def copy_reference(mib=256, reps=20):
     """Read + write bandwidth of torch's device copy of `mib` MiB (context for
     the sweep's roofline fraction)."""
@@ -506,6 +571,8 @@ def main():
                     help="time to 1e-4 of the reduced-byte and batched forms against plain float32 "
                          "(minutes)")
     ap.add_argument("--tol-forms-rho0", type=float, default=2.0)
+    ap.add_argument("--paper-sizes", action="store_true",
+                    help="the paper's runtime protocol at m = n from 100 to 20000")
     ap.add_argument("--large-only", action="store_true",
                     help="skip every section before the large instance (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -577,6 +644,8 @@ def main():
 
         # ---- the paper's runtime protocol: 10 runs x 100 iterations -----------------
         out["protocol_10x100"] = protocol_runs(ctx, bind)
+        # ---- one-off phases, reported apart from the iteration ----------------------
+        out["phases_ms"] = phase_times(ctx, bind)
         # ---- a plain device copy on the same box, for scale ---------------------------
         out["copy_reference"] = copy_reference()
 
@@ -661,6 +730,9 @@ def main():
         if args.tol_large:
             out["large"]["time_to_tol"] = time_to_tol_logged(ctx, C, p, q, args.tol_large_rho0,
                                                              args)
+
+    if args.paper_sizes:
+        out["paper_sizes"] = paper_sizes_section(ctx)
 
     if args.tol_forms:
         out["time_to_tol_forms"] = tol_forms_section(ctx, rho0=args.tol_forms_rho0)
