@@ -267,6 +267,7 @@ def protocol_runs(ctx, bind, runs=10, iters=100):
     rates = []
     for _ in range(runs):
         bind(0, iters + 1)
+        ctx.iterate(0)  # captures the graph: the protocol times its replay
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ctx.iterate(iters)
@@ -305,6 +306,7 @@ def paper_sizes_section(ctx, sizes=(100, 200, 500, 1000, 2000, 5000, 10000, 2000
         rates = []
         for _ in range(runs):
             ctx.bind(C, p, q, X, drot.make_params(rho, 0.0, iters + 1, check_every=iters))
+            ctx.iterate(0)  # captures the graph: the protocol times its replay
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             ctx.iterate(iters)
