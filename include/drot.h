@@ -106,18 +106,29 @@ typedef enum { DROT_CACHE_AUTO = 0, DROT_CACHE_CACHED = 1, DROT_CACHE_STREAM = 2
  * float32 pairs for its row, column, <C,X> and dual-residual sums, and every
  * later combination (lanes, waves, tiles, the aux kernel) is in float64, so
  * each residual carries about one float32 rounding of its terms instead of
- * one per addition.  X stays float32.  Float64 problems ignore the flag;
+ * one per addition.  X stays float32.  Float64 problems, and problems on
+ * the one-workgroup path (drot_params), whose sums are all float64, ignore
+ * the flag;
  * combined with DROT_FLAG_SKIP_C it gives DROT_EUNSUPPORTED; ragged widths
  * (n not a multiple of 4) use the 4-byte path. */
 #define DROT_FLAG_COMPENSATED 0x8
 
+/* Small problems take a one-workgroup path: a dense cost with m <= 1024,
+ * n <= 512 and m n <= 65536, all sweep-schedule fields 0, cache_mode AUTO
+ * and neither DROT_FLAG_SKIP_C nor DROT_FLAG_TIME_SWEEP.  There a single
+ * workgroup of 1024 threads runs many whole iterations per launch (the same
+ * steps, state and stopping test, with every sum in float64), since at these
+ * sizes two launches per iteration would cost more than the memory traffic;
+ * DROT_FLAG_NO_GRAPH has no effect on it.  Setting any tile field keeps a
+ * small problem on the sweep + aux path. */
 typedef struct {
   double rho;          /* penalty parameter rho > 0 (the paper uses rho0/(m+n)) */
   double tol;          /* stopping tolerance >= 0; 0 runs exactly max_iter iterations */
   int64_t max_iter;    /* iteration cap >= 1 */
   int32_t tol_mode;    /* drot_tol_mode */
   int32_t x0_mode;     /* drot_x0_mode */
-  int32_t check_every; /* iterations between host polls of the stop flag; 0 = 32 */
+  int32_t check_every; /* iterations between host polls of the stop flag; 0 = 32
+                          (1024 on the one-workgroup path) */
   int32_t flags;       /* DROT_FLAG_* */
   /* Sweep schedule (all 0 = automatic).  A workgroup owns a strip of
    * 64 * tile_chunks * (16 / element size) columns and the row blocks
@@ -239,8 +250,10 @@ int drot_iterate(drot_ctx *ctx, int64_t iters, void *stream);
  * whole graphs) with hipEvents on `stream`.  The fastest is then bound again
  * with the caller's other parameters, ready for drot_iterate from iteration
  * 0, and returned in *best (host; tile_rows, tile_chunks and tile_groups set).
- * *us_per_iter (host, may be NULL) receives its time per iteration.
- * X is overwritten by the trials, so the problem must have been bound with
+ * *us_per_iter (host, may be NULL) receives its time per iteration.  A
+ * problem on the one-workgroup path (drot_params) has no tile variants: it is
+ * timed as bound (`iters` iterations, 0 = 256), bound again, and *best is the
+ * caller's parameters.  X is overwritten by the trials, so the problem must have been bound with
  * x0_mode = DROT_X0_PQ (else DROT_EUNSUPPORTED); DROT_ESTATE without a bound
  * problem.  Blocks until done. */
 int drot_tune(drot_ctx *ctx, int64_t iters, drot_params *best, double *us_per_iter,

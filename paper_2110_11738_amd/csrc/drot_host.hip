@@ -79,6 +79,10 @@ struct drot_ctx {
   SweepArgs sa{};
   bool finished = false;
 
+  // Small problems iterate in one workgroup (small_kernel) instead of
+  // sweep + aux launches.
+  bool small = false;
+
   // Iterations enqueued since bind (the skip-C schedule alternates by parity).
   bool skipc = false;
   int64_t enq = 0;
@@ -297,7 +301,7 @@ int launch_iteration(drot_ctx* c, hipStream_t s, hipEvent_t e0, hipEvent_t e1, i
 // Iterations per graph / per host poll (even under the skip-C schedule, so
 // that every graph starts with a C-reading iteration).
 int group_size(const drot_ctx* c) {
-  int g = c->prm.check_every > 0 ? c->prm.check_every : 32;
+  int g = c->prm.check_every > 0 ? c->prm.check_every : (c->small ? 1024 : 32);
   if (c->skipc && (g & 1)) ++g;
   return g;
 }
@@ -553,6 +557,11 @@ int drot_bind_cost(drot_ctx* c, int64_t m, int64_t n, int dtype, const drot_cost
   c->args.nu0 = nu0;
   c->geo = g;
   c->skipc = (prm->flags & DROT_FLAG_SKIP_C) != 0;
+  c->small = cost->kind == DROT_COST_DENSE &&
+             !(prm->flags & (DROT_FLAG_SKIP_C | DROT_FLAG_TIME_SWEEP)) &&
+             prm->tile_rows == 0 && prm->tile_chunks == 0 && prm->tile_unroll == 0 &&
+             prm->tile_groups == 0 && prm->cache_mode == DROT_CACHE_AUTO &&
+             small_fits(dtype, m, n);
   c->enq = 0;
   c->sweep_ms = 0.0;
   c->sweep_n = 0;
@@ -671,6 +680,17 @@ extern "C" int drot_iterate(drot_ctx* c, int64_t iters, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   const bool timed = (c->prm.flags & DROT_FLAG_TIME_SWEEP) != 0;
   c->finished = false;
+  if (c->small) {
+    // Bounded launches; the kernel stops by itself at the stopping test.
+    constexpr int64_t kChunk = 4096;
+    while (iters > 0) {
+      const int64_t k = std::min(iters, kChunk);
+      HIP_TRY(launch_small(c->dtype, c->sa, k, s));
+      c->enq += k;
+      iters -= k;
+    }
+    return DROT_OK;
+  }
   if (c->prm.flags & DROT_FLAG_NO_GRAPH) return run_eager(c, s, iters);
   if ((rc = ensure_graph(c))) return rc;
   const int G = group_size(c);
@@ -707,6 +727,37 @@ extern "C" int drot_tune(drot_ctx* c, int64_t iters, drot_params* best, double* 
   hipStream_t s = (hipStream_t)stream;
   const auto A = c->args;
   const drot_params user = c->prm;
+  if (c->small) {
+    // The one-workgroup path has no tile variants: time it, bind again, and
+    // return the caller's parameters.
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      return fail(DROT_EDEVICE, "hipEventCreate failed");
+    }
+    drot_params t = user;
+    t.tol = 0.0;
+    t.max_iter = 2 * (iters > 0 ? iters : 256) + 1;
+    float ms = 0.f;
+    rc = drot_bind_cost(c, A.m, A.n, c->dtype, &A.cost, A.p, A.q, &t, A.X, A.ldx, A.mu0, A.nu0,
+                        stream);
+    const int64_t k = iters > 0 ? iters : 256;
+    if (!rc) rc = drot_iterate(c, k, stream);
+    if (!rc && (hipEventRecord(e0, s) != hipSuccess || drot_iterate(c, k, stream) != DROT_OK ||
+                hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      rc = fail(DROT_EDEVICE, "timing the one-workgroup path failed");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if ((rc = drot_bind_cost(c, A.m, A.n, c->dtype, &A.cost, A.p, A.q, &user, A.X, A.ldx, A.mu0,
+                             A.nu0, stream)))
+      return rc;
+    *best = user;
+    if (us_per_iter) *us_per_iter = ms * 1e3 / (double)k;
+    return DROT_OK;
+  }
   drot_params trial = user;
   trial.tol = 0.0;
   trial.flags &= ~(DROT_FLAG_NO_GRAPH | DROT_FLAG_TIME_SWEEP);

@@ -17,6 +17,21 @@ constexpr int kTraceWidth = 8;
 constexpr int kAuxCols = 64;       // columns per aux column workgroup
 constexpr int kAuxRows = kWave;    // rows per aux row workgroup
 constexpr int kAuxSplitMin = 256;  // from this many aux workgroups: separate finishing launch
+// One-workgroup iteration for small problems (see small_kernel).
+// One-workgroup path: kSmallBlock threads (16 waves) hold the plan and the
+// cost in registers, small_slots(dtype) entries of each per thread: wave w
+// owns rows w, w + 16, ... (small_rows of them), lane l the columns
+// l, l + 64, ... (small_cols of them, a power of two up to 8).
+constexpr int kSmallBlock = 1024;
+constexpr int kSmallWaves = kSmallBlock / kWave;
+constexpr int small_slots(int dtype) { return dtype == 0 ? 32 : 16; }
+constexpr int small_cols(int64_t n) {
+  return n <= kWave ? 1 : n <= 2 * kWave ? 2 : n <= 4 * kWave ? 4 : n <= 8 * kWave ? 8 : 0;
+}
+constexpr bool small_fits(int dtype, int64_t m, int64_t n) {
+  return m >= 1 && n >= 1 && small_cols(n) > 0 &&
+         m <= (int64_t)kSmallWaves * (small_slots(dtype) / small_cols(n));
+}
 
 // Workgroups of one aux launch: column groups of kAuxCols, then row groups of
 // kAuxRows.
@@ -155,6 +170,8 @@ hipError_t launch_sweep(int dtype, int mode, const TileCfg& t, const SweepArgs& 
 // `wide`: the float32 iteration's partials are float64 (compensated sweep).
 hipError_t launch_aux(int dtype, int mode, const SweepArgs& a, hipStream_t s, bool wide = false);
 hipError_t launch_prep(const SweepArgs& a, hipStream_t s);
+// `iters` iterations of a small problem in one one-workgroup launch.
+hipError_t launch_small(int dtype, const SweepArgs& a, int64_t iters, hipStream_t s);
 hipError_t launch_maxc(const SweepArgs& a, hipStream_t s);
 
 // Batched problems: `args` (device) holds one SweepArgs per problem; the work

@@ -677,6 +677,324 @@ __global__ __launch_bounds__(kWave) void finish_batch_kernel(const SweepArgs* __
   finish_body<MODE>(a);
 }
 
+// ---------------------------------------------------------------------------
+// Small problems: the whole iteration in one workgroup of kSmallBlock
+// threads, `iters` iterations per launch.  Below a few hundred kilobytes per
+// iteration the two-launch iteration is bound by the fixed cost of its
+// launches and of its dependent memory round trips, not by bandwidth; here
+// the plan and the cost stay in registers for the whole launch and three
+// workgroup barriers per iteration are the only synchronisation.  Same
+// steps, state and stopping test as sweep + aux:
+//  - wave w holds rows w, w + 16, ... (RT of them), lane l the columns
+//    l, l + 64, ... (NCOL of them); step 4 on these entries, with the row
+//    sums by DPP and the column partials combined over the 16 waves in LDS
+//    in a fixed order;
+//  - thread i finishes row i and thread j column j (steps 5-8);
+//  - wave 0 combines the eight scalar sums in a fixed order and takes the
+//    scalar step (the shifts of step 3, alpha, the stopping test), and
+//    broadcasts it through LDS.
+// The workgroup runs on one compute unit, so the cost of an iteration is
+// its instruction count: work that only one wave needs runs in one wave.
+// All sums of this path are float64.
+// ---------------------------------------------------------------------------
+
+// Sum over each row of 16 lanes (fixed order); every lane of the row gets it.
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp<0xB1>(v);   // pairs
+  v += dpp<0x4E>(v);   // quads
+  v += dpp<0x141>(v);  // half-row mirror: 8
+  v += dpp<0x140>(v);  // row mirror: 16
+  return v;
+}
+
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const unsigned long long bits = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)(bits & 0xffffffffull), l);
+  const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(bits >> 32), l);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+template <typename T, int NCOL>
+__global__ __launch_bounds__(kSmallBlock) void small_kernel(SweepArgs a, int64_t iters) {
+  constexpr int NW = kSmallWaves;
+  constexpr int RT = small_slots(std::is_same<T, float>::value ? 0 : 1) / NCOL;
+  constexpr int NC = kWave * NCOL;  // columns covered
+  constexpr int RG = RT < 4 ? RT : 4;  // rows per batch of DPP row sums
+  __shared__ T rowsh[NW * RT];
+  __shared__ T colsh[NC];
+  __shared__ double usum[NW * RT];
+  __shared__ double colp[NW][NC];
+  __shared__ double red[NW][8];
+  // Per-row and per-column vectors of steps 5-8 (a, phi~, p and b, psi~, q),
+  // each entry used only by its own thread; kept here to free registers.
+  __shared__ double rv[3][NW * RT];
+  __shared__ double cv[3][NC];
+  __shared__ double rec[6];  // the latest iteration's record, from thread 0
+  __shared__ double bc[4];   // the scalar step's results, from thread 0
+
+  DevState* st = a.st;
+  const StateIn sv = load_state(st);
+  if (sv.done) return;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const int m = (int)a.g.m, n = (int)a.g.n;
+  const int64_t ldc = a.g.ldc, ldx = a.g.ldx;
+  const T* __restrict__ C = static_cast<const T*>(a.C);
+  T* __restrict__ X = static_cast<T*>(a.X);
+  const double rho = sv.rho;
+  const T rhoT = (T)rho;
+  const bool own_r = tid < m, own_c = tid < n;
+  // rows held by this wave: wave + NW t for t < nrows
+  const int nrows = m > wave ? (m - wave + NW - 1) / NW : 0;
+  bool jv[NCOL];
+#pragma unroll
+  for (int c = 0; c < NCOL; ++c) jv[c] = lane + kWave * c < n;
+
+  T xr[RT][NCOL], cr[RT][NCOL];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) {
+    const int64_t i = wave + NW * t;
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) {
+      const int j = lane + kWave * c;
+      const bool v = t < nrows && jv[c];
+      xr[t][c] = v ? X[i * ldx + j] : (T)0;
+      cr[t][c] = v ? C[i * ldc + j] : (T)0;
+    }
+  }
+
+  if (own_r) {
+    rv[0][tid] = a.a[tid];
+    rv[1][tid] = a.phi64[tid];
+    rv[2][tid] = (double)static_cast<const T*>(a.p)[tid];
+    rowsh[tid] = static_cast<const T*>(a.phiT)[tid];
+  }
+  if (own_c) {
+    cv[0][tid] = a.b[tid];
+    cv[1][tid] = a.psi64[tid];
+    cv[2][tid] = (double)static_cast<const T*>(a.q)[tid];
+  }
+  if (tid < NC) colsh[tid] = own_c ? static_cast<const T*>(a.psiT)[tid] : (T)0;
+  double alpha = sv.alpha, cphi = sv.cphi, cpsi = sv.cpsi;
+  int64_t k = sv.iter;
+  int done = 0, status = 0;
+  __syncthreads();
+
+  for (int64_t it = 0; it < iters; ++it) {
+    // Step 4 on the held entries, with the row sums, the column partials
+    // and the stopping-test partials <C,X> and |[.]_+|^2.
+    const T shift = (T)(cphi + cpsi);
+    T colv[NCOL];
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) colv[c] = colsh[lane + kWave * c];
+    double cacc[NCOL];
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) cacc[c] = 0.0;
+    double s0 = 0.0, s1 = 0.0;
+    // The cost is loop-invariant; without this the compiler hoists rho c and
+    // its float64 widening out of the loop, which needs three times the
+    // registers and spills.
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) asm volatile("" : "+v"(cr[t][c]));
+#pragma unroll
+    for (int t0 = 0; t0 < RT; t0 += RG) {
+      double rs[RG];
+#pragma unroll
+      for (int u = 0; u < RG; ++u) {
+        const int t = t0 + u;
+        rs[u] = 0.0;
+        if (t < nrows) {
+          const T rowv = rowsh[wave + NW * t] + shift;
+#pragma unroll
+          for (int c = 0; c < NCOL; ++c) {
+            if (jv[c]) {
+              const T tt = rowv + colv[c] - mul_rounded<T>(rhoT, cr[t][c]);
+              const T tp = tt > (T)0 ? tt : (T)0;
+              s1 += (double)tp * (double)tp;
+              const T y = xr[t][c] + tt;
+              const T xn = y > (T)0 ? y : (T)0;
+              xr[t][c] = xn;
+              rs[u] += (double)xn;
+              cacc[c] += (double)xn;
+              s0 += (double)cr[t][c] * (double)xn;
+            }
+          }
+        }
+      }
+      if (t0 < nrows) {
+        wave_sum_n(rs);
+        if (lane == 0)
+#pragma unroll
+          for (int u = 0; u < RG; ++u)
+            if (t0 + u < nrows) usum[wave + NW * (t0 + u)] = rs[u];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) colp[wave][lane + kWave * c] = cacc[c];
+    __syncthreads();
+
+    // Steps 5-8 per row and column, and the eight scalar sums.  Waves with
+    // no row or column owner only reduce their sweep partials.
+    if (wave * kWave < (m > n ? m : n)) {
+      double e[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, s0, s1};
+      if (own_r) {
+        const double ai = rv[0][tid], pi = rv[2][tid];
+        const double r = usum[tid] - pi;
+        const double ph = (ai - 2.0 * r) / (double)n;
+        rv[0][tid] = ai - r;
+        rv[1][tid] = ph;
+        rowsh[tid] = (T)ph;
+        e[0] = r;
+        e[1] = r * r;
+        e[2] = pi * ph;
+      }
+      if (own_c) {
+        double v = colp[0][tid];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) v += colp[w][tid];
+        const double bj = cv[0][tid], qj = cv[2][tid];
+        const double s = v - qj;
+        const double ps = (bj - 2.0 * s) / (double)m;
+        cv[0][tid] = bj - s;
+        cv[1][tid] = ps;
+        colsh[tid] = (T)ps;
+        e[3] = s;
+        e[4] = s * s;
+        e[5] = qj * ps;
+      }
+      wave_sum_n(e);
+      if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) red[wave][q] = e[q];
+    } else {
+      double e[2] = {s0, s1};
+      wave_sum_n(e);
+      if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) red[wave][q] = 0.0;
+        red[wave][6] = e[0];
+        red[wave][7] = e[1];
+      }
+    }
+    __syncthreads();
+
+    // The scalar step in wave 0: lane l adds red[l % 16][l / 16] and
+    // red[l % 16][4 + l / 16] over its row of 16 lanes (a fixed order).
+    if (wave == 0) {
+      const double v0 = row16_sum(red[lane & 15][lane >> 4]);
+      const double v1 = row16_sum(red[lane & 15][4 + (lane >> 4)]);
+      double acc[8];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        acc[q] = read_lane(v0, 16 * q);
+        acc[4 + q] = read_lane(v1, 16 * q);
+      }
+      const double beta = acc[0] / (double)(m + n);
+      const double cc = 2.0 * beta - alpha;
+      const double nphi = cc / (double)n, npsi = cc / (double)m;
+      const double pobj = acc[6];
+      const double dobj = (acc[2] + nphi * sv.sum_p + acc[5] + npsi * sv.sum_q) / rho;
+      const double gap = fabs(pobj - dobj);
+      const double rp = sqrt(acc[1] + acc[4]);
+      const double rd = sqrt(acc[7]) / rho;
+      const double ep = rp / fmax(sv.norm_pq, 1e-300);
+      const double ed = rd / fmax(sv.norm_c, 1e-300);
+      const double eg = gap / fmax(fmax(fabs(pobj), fabs(dobj)), 1e-300);
+      const double test = sv.tol_mode ? fmax(rp, fmax(rd, gap)) : fmax(ep, fmax(ed, eg));
+      const double alpha_next = alpha - beta;
+      const int64_t kn = k + 1;
+      int dn = 0;
+      if (!finite_d(test) || !finite_d(alpha_next) || !finite_d(cc) || !finite_d(rp)) {
+        dn = 1;
+        status = -3;
+      } else if (test <= sv.tol) {
+        dn = 1;
+        status = 0;
+      } else if (kn >= sv.max_iter) {
+        dn = 1;
+        status = 1;
+      }
+      if (lane == 0) {
+        const uint64_t now = wall_clock64();
+        const int64_t slot = kn - 1 < a.trace_cap ? kn - 1 : (kn - 1) % a.trace_cap;
+        double* tr = a.trace + slot * kTraceWidth;
+        tr[0] = pobj;
+        tr[1] = dobj;
+        tr[2] = rp;
+        tr[3] = rd;
+        tr[4] = gap;
+        tr[5] = test;
+        tr[6] = (double)(now - sv.t_start) / a.wall_rate;
+        tr[7] = (double)kn;
+        rec[0] = pobj;
+        rec[1] = dobj;
+        rec[2] = rp;
+        rec[3] = rd;
+        rec[4] = gap;
+        rec[5] = test;
+        bc[0] = nphi;
+        bc[1] = npsi;
+        bc[2] = alpha_next;
+        bc[3] = (double)dn;
+      }
+    }
+    __syncthreads();
+    cphi = bc[0];
+    cpsi = bc[1];
+    alpha = bc[2];
+    done = bc[3] != 0.0;
+    ++k;
+    if (done) break;
+  }
+
+  // A fresh base for the stores, so that the load addresses are not kept
+  // live (in registers or scratch) through the iteration.
+  T* Xw = X;
+  int64_t ldw = ldx;
+  int lw = lane, ww = wave;
+  asm volatile("" : "+s"(Xw), "+s"(ldw), "+v"(lw), "+v"(ww));
+#pragma unroll
+  for (int t = 0; t < RT; ++t) {
+    const int64_t i = ww + NW * t;
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c)
+      if (t < nrows && jv[c]) Xw[i * ldw + lw + kWave * c] = xr[t][c];
+  }
+  if (own_r) {
+    a.a[tid] = rv[0][tid];
+    a.phi64[tid] = rv[1][tid];
+    static_cast<T*>(a.phiT)[tid] = (T)rv[1][tid];
+  }
+  if (own_c) {
+    a.b[tid] = cv[0][tid];
+    a.psi64[tid] = cv[1][tid];
+    static_cast<T*>(a.psiT)[tid] = (T)cv[1][tid];
+  }
+  if (tid == 0) {
+    const uint64_t now = wall_clock64();
+    st->alpha = alpha;
+    st->cphi = cphi;
+    st->cpsi = cpsi;
+    st->iter = k;
+    st->t_last = now;
+    if (k > sv.iter) {
+      st->pobj = rec[0];
+      st->dobj = rec[1];
+      st->rp = rec[2];
+      st->rd = rec[3];
+      st->gap = rec[4];
+      st->test = rec[5];
+    }
+    if (done) {
+      st->done = 1;
+      st->status = status;
+      st->stop_iter = k;
+      st->t_stop = now;
+    }
+  }
+}
+
 // Batched form: work item = (problem, aux workgroup of that problem).
 template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void aux_batch_kernel(const SweepArgs* __restrict__ args,
@@ -1317,6 +1635,27 @@ hipError_t launch_batch_step(int dtype, int mode, const TileCfg& t, const SweepA
 hipError_t launch_prep_batch(const SweepArgs* args, int count, hipStream_t s) {
   hipLaunchKernelGGL(prep_batch_kernel, dim3((unsigned)count), dim3(kBlock), 0, s, args);
   return hipGetLastError();
+}
+
+namespace {
+template <typename T>
+hipError_t small_type(const SweepArgs& a, int64_t iters, hipStream_t s) {
+  const dim3 grid(1), block(kSmallBlock);
+  switch (small_cols(a.g.n)) {
+    case 1: hipLaunchKernelGGL((small_kernel<T, 1>), grid, block, 0, s, a, iters); break;
+    case 2: hipLaunchKernelGGL((small_kernel<T, 2>), grid, block, 0, s, a, iters); break;
+    case 4: hipLaunchKernelGGL((small_kernel<T, 4>), grid, block, 0, s, a, iters); break;
+    case 8: hipLaunchKernelGGL((small_kernel<T, 8>), grid, block, 0, s, a, iters); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_small(int dtype, const SweepArgs& a, int64_t iters, hipStream_t s) {
+  // The kernel's register and LDS arrays are sized for small_fits shapes.
+  if (!small_fits(dtype, a.g.m, a.g.n)) return hipErrorInvalidValue;
+  return dtype == 0 ? small_type<float>(a, iters, s) : small_type<double>(a, iters, s);
 }
 
 hipError_t launch_maxc(const SweepArgs& a, hipStream_t s) {

@@ -61,10 +61,14 @@ def _rel_max(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
-# The last two shapes need 257 aux workgroups, which takes the split aux form
-# (publish-only aux launch plus a separate finishing launch).
-SHAPES = [(1, 1), (1, 7), (9, 1), (3, 5), (37, 129), (300, 260), (513, 1030), (64, 2048),
-          (16384, 64), (64, 16384)]
+# With the default parameters the one-workgroup path takes the first ten
+# shapes in float32 and the first eight in float64 (512 x 64
+# and 64 x 512 are its float32 row and column limits, 256 x 64 and 32 x 512
+# its float64 ones); the rest take sweep + aux.  The last two need 257 aux
+# workgroups, which takes the split aux form (publish-only aux launch plus a
+# separate finishing launch).
+SHAPES = [(1, 1), (1, 7), (9, 1), (3, 5), (37, 129), (100, 100), (256, 64), (32, 512),
+          (512, 64), (64, 512), (300, 260), (513, 1030), (64, 2048), (16384, 64), (64, 16384)]
 
 
 @pytest.mark.parametrize("dtype", ["float64", "float32"])
@@ -92,6 +96,24 @@ def test_trajectory_parity(ctx, dtype, m, n):
         ev = ref.evaluate(inst.C, inst.p, inst.q, inst.rho, R.X, R.phi, R.psi)
         floor = (16 * 2.0 ** -24 if dtype == "float32" else 1e-13) * ev["norm_pq"]
         assert abs(res["r_primal"] - ev["r_primal"]) <= 1e-3 * ev["r_primal"] + floor
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("m,n", [(1, 7), (37, 129), (100, 100)], ids=lambda v: str(v))
+def test_small_shapes_on_tiled_path(ctx, dtype, m, n):
+    """A tile parameter moves a small problem off the one-workgroup path onto
+    sweep + aux; both must follow the oracle's trajectory."""
+    inst = _rounded(config_mixture_2d(11, m, n), dtype)
+    K = 25
+    R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=K, trace=True)
+    tx, td, to = TOL[dtype]
+    for kw in ({}, {"tile_rows": 16}):
+        print(f"[small/tiled] {dtype} {m}x{n} {kw}", flush=True)
+        Xg, res, mu, nu = _run(ctx, inst, dtype, K, **kw)
+        assert res["iters"] == K
+        assert _rel_max(Xg, R.X) <= tx
+        assert _rel_max(mu, R.mu) <= td and _rel_max(nu, R.nu) <= td
+        assert abs(res["objective"] - R.info["pobj"]) <= to * abs(R.info["pobj"])
 
 
 @pytest.mark.parametrize("dtype", ["float64", "float32"])
@@ -389,6 +411,19 @@ def test_tune_binds_a_valid_variant(ctx):
     with pytest.raises(drot.DrotError) as e:
         ctx.tune(8)
     assert e.value.code == drot.EUNSUPPORTED
+    # a problem on the one-workgroup path keeps the caller's parameters
+    inst = round_to(config_mixture_2d(13, 100, 120), np.float32)
+    C, p, q = _upload(inst, "float32")
+    X = torch.empty_like(C)
+    ctx.bind(C, p, q, X, drot.make_params(inst.rho, 0.0, 20))
+    best, us = ctx.tune(16)
+    assert best.tile_rows == 0 and best.tile_chunks == 0 and best.max_iter == 20 and us > 0
+    ctx.iterate(20)
+    res = ctx.finish()
+    torch.cuda.synchronize()
+    R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=20)
+    assert res["iters"] == 20
+    assert _rel_max(X.double().cpu().numpy(), R.X) <= TOL["float32"][0]
 
 
 @pytest.mark.parametrize("flags", ["graph", "eager"])
