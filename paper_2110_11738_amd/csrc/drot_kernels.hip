@@ -687,15 +687,17 @@ __global__ __launch_bounds__(kWave) void finish_batch_kernel(const SweepArgs* __
 // steps, state and stopping test as sweep + aux:
 //  - wave w holds rows w, w + 16, ... (RT of them), lane l the columns
 //    l, l + 64, ... (NCOL of them); step 4 on these entries, with the row
-//    sums by DPP and the column partials combined over the 16 waves in LDS
-//    in a fixed order;
+//    and column partials combined in LDS in a fixed order;
 //  - thread i finishes row i and thread j column j (steps 5-8);
 //  - wave 0 combines the eight scalar sums in a fixed order and takes the
 //    scalar step (the shifts of step 3, alpha, the stopping test), and
 //    broadcasts it through LDS.
 // The workgroup runs on one compute unit, so the cost of an iteration is
-// its instruction count: work that only one wave needs runs in one wave.
-// All sums of this path are float64.
+// its instruction count: work that only one wave needs runs in one wave,
+// and a row's sum goes through LDS (each lane's partial, added up by the
+// row's thread) instead of a DPP reduction per row.  Each lane's partial
+// sums (of at most 32 entries) are in the problem's type, as in the sweep;
+// everything after them is float64.
 // ---------------------------------------------------------------------------
 
 // Sum over each row of 16 lanes (fixed order); every lane of the row gets it.
@@ -719,10 +721,9 @@ __global__ __launch_bounds__(kSmallBlock) void small_kernel(SweepArgs a, int64_t
   constexpr int NW = kSmallWaves;
   constexpr int RT = small_slots(std::is_same<T, float>::value ? 0 : 1) / NCOL;
   constexpr int NC = kWave * NCOL;  // columns covered
-  constexpr int RG = RT < 4 ? RT : 4;  // rows per batch of DPP row sums
   __shared__ T rowsh[NW * RT];
   __shared__ T colsh[NC];
-  __shared__ double usum[NW * RT];
+  __shared__ T rowp[NW * RT][kWave];  // each lane's partial of each row
   __shared__ double colp[NW][NC];
   __shared__ double red[NW][8];
   // Per-row and per-column vectors of steps 5-8 (a, phi~, p and b, psi~, q),
@@ -786,10 +787,10 @@ __global__ __launch_bounds__(kSmallBlock) void small_kernel(SweepArgs a, int64_t
     T colv[NCOL];
 #pragma unroll
     for (int c = 0; c < NCOL; ++c) colv[c] = colsh[lane + kWave * c];
-    double cacc[NCOL];
+    T cacc[NCOL];
 #pragma unroll
-    for (int c = 0; c < NCOL; ++c) cacc[c] = 0.0;
-    double s0 = 0.0, s1 = 0.0;
+    for (int c = 0; c < NCOL; ++c) cacc[c] = (T)0;
+    T s0 = (T)0, s1 = (T)0;
     // The cost is loop-invariant; without this the compiler hoists rho c and
     // its float64 widening out of the loop, which needs three times the
     // registers and spills.
@@ -798,49 +799,51 @@ __global__ __launch_bounds__(kSmallBlock) void small_kernel(SweepArgs a, int64_t
 #pragma unroll
       for (int c = 0; c < NCOL; ++c) asm volatile("" : "+v"(cr[t][c]));
 #pragma unroll
-    for (int t0 = 0; t0 < RT; t0 += RG) {
-      double rs[RG];
+    for (int t = 0; t < RT; ++t) {
+      if (t < nrows) {
+        const T rowv = rowsh[wave + NW * t] + shift;
+        T rs = (T)0;
 #pragma unroll
-      for (int u = 0; u < RG; ++u) {
-        const int t = t0 + u;
-        rs[u] = 0.0;
-        if (t < nrows) {
-          const T rowv = rowsh[wave + NW * t] + shift;
-#pragma unroll
-          for (int c = 0; c < NCOL; ++c) {
-            if (jv[c]) {
-              const T tt = rowv + colv[c] - mul_rounded<T>(rhoT, cr[t][c]);
-              const T tp = tt > (T)0 ? tt : (T)0;
-              s1 += (double)tp * (double)tp;
-              const T y = xr[t][c] + tt;
-              const T xn = y > (T)0 ? y : (T)0;
-              xr[t][c] = xn;
-              rs[u] += (double)xn;
-              cacc[c] += (double)xn;
-              s0 += (double)cr[t][c] * (double)xn;
-            }
+        for (int c = 0; c < NCOL; ++c) {
+          if (jv[c]) {
+            const T tt = rowv + colv[c] - mul_rounded<T>(rhoT, cr[t][c]);
+            const T tp = tt > (T)0 ? tt : (T)0;
+            s1 += tp * tp;
+            const T y = xr[t][c] + tt;
+            const T xn = y > (T)0 ? y : (T)0;
+            xr[t][c] = xn;
+            rs += xn;
+            cacc[c] += xn;
+            s0 += cr[t][c] * xn;
           }
         }
-      }
-      if (t0 < nrows) {
-        wave_sum_n(rs);
-        if (lane == 0)
-#pragma unroll
-          for (int u = 0; u < RG; ++u)
-            if (t0 + u < nrows) usum[wave + NW * (t0 + u)] = rs[u];
+        rowp[wave + NW * t][lane] = rs;
       }
     }
 #pragma unroll
-    for (int c = 0; c < NCOL; ++c) colp[wave][lane + kWave * c] = cacc[c];
+    for (int c = 0; c < NCOL; ++c) colp[wave][lane + kWave * c] = (double)cacc[c];
     __syncthreads();
 
     // Steps 5-8 per row and column, and the eight scalar sums.  Waves with
     // no row or column owner only reduce their sweep partials.
     if (wave * kWave < (m > n ? m : n)) {
-      double e[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, s0, s1};
+      double e[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, (double)s0, (double)s1};
       if (own_r) {
+        // the row's 64 lane partials, in four interleaved chains; thread i
+        // starts at lane i mod 64 so that the threads of a wave read
+        // different banks
+        double u4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+        for (int u0 = 0; u0 < kWave; u0 += 8) {
+          T v8[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v8[u] = rowp[tid][(u0 + u + tid) & (kWave - 1)];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) u4[u & 3] += (double)v8[u];
+        }
+        const double usum = (u4[0] + u4[1]) + (u4[2] + u4[3]);
         const double ai = rv[0][tid], pi = rv[2][tid];
-        const double r = usum[tid] - pi;
+        const double r = usum - pi;
         const double ph = (ai - 2.0 * r) / (double)n;
         rv[0][tid] = ai - r;
         rv[1][tid] = ph;
@@ -868,7 +871,7 @@ __global__ __launch_bounds__(kSmallBlock) void small_kernel(SweepArgs a, int64_t
 #pragma unroll
         for (int q = 0; q < 8; ++q) red[wave][q] = e[q];
     } else {
-      double e[2] = {s0, s1};
+      double e[2] = {(double)s0, (double)s1};
       wave_sum_n(e);
       if (lane == 0) {
 #pragma unroll
