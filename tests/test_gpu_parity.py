@@ -116,6 +116,32 @@ def test_small_shapes_on_tiled_path(ctx, dtype, m, n):
         assert abs(res["objective"] - R.info["pobj"]) <= to * abs(R.info["pobj"])
 
 
+@pytest.mark.parametrize("check_every", [1, 7, 0])
+def test_small_path_launch_chunks_and_stop(ctx, check_every):
+    """The one-workgroup path runs up to 4096 iterations per launch and stops
+    inside a launch: 5000 iterations (two launches) follow the oracle's
+    trajectory with a continuous trace, and a solve to 1e-6 (about 60 000
+    iterations) stops at the oracle's iteration whatever the polling
+    interval."""
+    inst = config_mixture_2d(12, 40, 70)
+    K = 5000
+    print(f"[small] chunks K={K} check_every={check_every}", flush=True)
+    Xg, res, mu, nu = _run(ctx, inst, "float64", K, check_every=check_every)
+    R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=K, trace=True)
+    assert res["iters"] == K
+    assert _rel_max(Xg, R.X) <= 1e-9
+    assert _rel_max(mu, R.mu) <= 1e-8 and _rel_max(nu, R.nu) <= 1e-8
+    tr = ctx.trace(1, K)
+    np.testing.assert_array_equal(tr[:, 7], np.arange(1, K + 1))
+    np.testing.assert_allclose(tr[:, 0], R.trace[:, 0], rtol=1e-9)
+    Xg, res, mu, nu = _run(ctx, inst, "float64", 200_000, tol=1e-6, check_every=check_every)
+    R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 1e-6, max_iter=200_000)
+    print(f"    stop: gpu {res['iters']} oracle {R.info['iters']}", flush=True)
+    assert res["status"] == 0
+    assert abs(res["iters"] - R.info["iters"]) <= 1
+    assert abs(res["objective"] - R.info["pobj"]) <= 1e-9 * abs(R.info["pobj"])
+
+
 @pytest.mark.parametrize("dtype", ["float64", "float32"])
 def test_trace_matches_oracle(ctx, dtype):
     inst = _rounded(config_mixture_2d(8, 200, 333), dtype)
@@ -331,15 +357,17 @@ def test_compensated_flag_rules(ctx):
     assert e.value.code == drot.EUNSUPPORTED
 
 
-@pytest.mark.parametrize("flags", ["plain", "skipc"])
+@pytest.mark.parametrize("flags", ["plain", "skipc", "small"])
 def test_checkpoint_resume_continues_bit_exactly(ctx, flags):
     """Checkpoint after 20 iterations, continue 40 in the same context; a
     second context bound with the saved plan and resumed from the checkpoint
-    ends on the same plan, result and trace, bit for bit."""
+    ends on the same plan, result and trace, bit for bit ("small": a shape on
+    the one-workgroup path)."""
     torch = _torch()
     from paper_2110_11738_amd import drot
     fl = drot.FLAG_SKIP_C if flags == "skipc" else 0
-    inst = round_to(config_mixture_2d(16, 300, 520), np.float32)
+    m, n = (40, 70) if flags == "small" else (300, 520)
+    inst = round_to(config_mixture_2d(16, m, n), np.float32)
     C, p, q = _upload(inst, "float32")
     X = torch.empty_like(C)
     ctx.bind(C, p, q, X, drot.make_params(inst.rho, 0.0, 60, check_every=8, flags=fl))
