@@ -324,6 +324,38 @@ def paper_sizes_section(ctx, sizes=(100, 200, 500, 1000, 2000, 5000, 10000, 2000
     return out
 
 
+def small_section(ctx, sizes=(100, 128), iters=2000, warm=200):
+    """Small problems (the paper's generator, float32, rho0 = 1/ln m): the
+    one-workgroup path that the default parameters select, against sweep +
+    aux forced by a tile parameter, iterations/s over `iters` iterations."""
+    import math
+    import numpy as np
+    import torch
+    from gen import paper_protocol
+    from paper_2110_11738_amd import drot
+    out = []
+    for m in sizes:
+        inst = paper_protocol(0, m, rho0=1.0 / math.log(m))
+        C = torch.from_numpy(inst.C.astype(np.float32)).cuda()
+        p = torch.from_numpy(inst.p.astype(np.float32)).cuda()
+        q = torch.from_numpy(inst.q.astype(np.float32)).cuda()
+        X = torch.empty_like(C)
+        row = {"m": m, "n": m}
+        for name, tr in (("one_workgroup", 0), ("sweep_aux", 16)):
+            ctx.bind(C, p, q, X, drot.make_params(inst.rho, 0.0, warm + iters + 1, tile_rows=tr))
+            ctx.iterate(warm)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.iterate(iters)
+            torch.cuda.synchronize()
+            row[name + "_iter_per_s"] = iters / (time.perf_counter() - t0)
+        row["speedup"] = row["one_workgroup_iter_per_s"] / row["sweep_aux_iter_per_s"]
+        log(f"small {m}x{m}: one workgroup {row['one_workgroup_iter_per_s']:.0f} it/s, "
+            f"sweep + aux {row['sweep_aux_iter_per_s']:.0f} it/s ({row['speedup']:.2f}x)")
+        out.append(row)
+    return out
+
+
 def phase_times(ctx, bind, reps=5):
     """Host wall time of the phases around the iteration: bind (validation,
     initialisation pass X_0 = p q^T with its sums, and the check of the
@@ -565,6 +597,7 @@ def main():
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-skipc", action="store_true")
+    ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuned runs")
     ap.add_argument("--tol-large", action="store_true",
                     help="also time the large instance to the 1e-4 test (minutes)")
@@ -692,6 +725,8 @@ def main():
         out["precision"] = precision_section(ctx)
     if not args.no_batch and not args.large_only:
         out["batch"] = batch_section(ctx)
+    if not args.no_small and not args.large_only:
+        out["small"] = small_section(ctx)
 
     # ---- 20000^2 roofline instance ----------------------------------------------
     if not args.no_large and args.large > 0:

@@ -236,7 +236,8 @@ int drot_bind(drot_ctx *ctx, int64_t m, int64_t n, int dtype, const void *C, int
               const double *mu0, const double *nu0, void *stream);
 
 /* Enqueue `iters` further iterations of Algorithm 1 (one sweep and one dual
- * update each) on `stream` without waiting.  Iterations after the stopping
+ * update each; on the one-workgroup path, launches of up to 4096 whole
+ * iterations) on `stream` without waiting.  Iterations after the stopping
  * test (or max_iter) has fired are no-ops on the device. */
 int drot_iterate(drot_ctx *ctx, int64_t iters, void *stream);
 
