@@ -230,15 +230,17 @@ def test_tile_shapes_agree_with_oracle(ctx, tile_rows, tile_chunks):
     assert _rel_max(Xg, R.X) <= TOL["float32"][0]
 
 
-def test_padded_leading_dimension_and_scalar_path(ctx):
-    """ldx > n with a ragged n (scalar path): padding columns stay untouched."""
+@pytest.mark.parametrize("m", [130, 100])
+def test_padded_leading_dimension_and_scalar_path(ctx, m):
+    """ldx > n with a ragged n (scalar path; 100 rows take the one-workgroup
+    path): padding columns stay untouched."""
     torch = _torch()
     from paper_2110_11738_amd import drot
-    inst = round_to(config_mixture_2d(6, 130, 203), np.float32)
+    inst = round_to(config_mixture_2d(6, m, 203), np.float32)
     C, p, q = _upload(inst, "float32")
-    Cpad = torch.full((130, 211), 7.0, dtype=torch.float32, device="cuda")[:, :203]
+    Cpad = torch.full((m, 211), 7.0, dtype=torch.float32, device="cuda")[:, :203]
     Cpad.copy_(C)
-    Xbig = torch.full((130, 210), -3.0, dtype=torch.float32, device="cuda")
+    Xbig = torch.full((m, 210), -3.0, dtype=torch.float32, device="cuda")
     X = Xbig[:, :203]
     prm = drot.make_params(inst.rho, 0.0, 20)
     X, res = ctx.solve(Cpad, p, q, prm, X=X)
