@@ -116,6 +116,40 @@ def test_small_shapes_on_tiled_path(ctx, dtype, m, n):
         assert abs(res["objective"] - R.info["pobj"]) <= to * abs(R.info["pobj"])
 
 
+def _small_fits(dtype, m, n):
+    """The one-workgroup path's shape rule (a power-of-two number of 64-column
+    groups up to 8, and 16 rows per 32 float32 or 16 float64 entries a thread
+    holds)."""
+    cols = next((c for c in (1, 2, 4, 8) if n <= 64 * c), 0)
+    slots = 32 if dtype == "float32" else 16
+    return cols > 0 and m <= 16 * (slots // cols)
+
+
+_RNG_SHAPES = np.random.default_rng(2024)
+RANDOM_SMALL = []
+while len(RANDOM_SMALL) < 8:
+    _m, _n = int(_RNG_SHAPES.integers(1, 513)), int(_RNG_SHAPES.integers(1, 513))
+    _dt = ("float32", "float64")[len(RANDOM_SMALL) % 2]
+    if _small_fits(_dt, _m, _n):
+        RANDOM_SMALL.append((_dt, _m, _n))
+
+
+@pytest.mark.parametrize("dtype,m,n", RANDOM_SMALL, ids=lambda v: str(v))
+def test_random_small_shapes_follow_oracle(ctx, dtype, m, n):
+    """Seeded random shapes inside the one-workgroup path's limits: 15
+    iterations against the oracle, with the default and a tiled schedule."""
+    inst = _rounded(config_mixture_2d(21, m, n), dtype)
+    K = 15
+    R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=K)
+    tx, td, to = TOL[dtype]
+    for kw in ({}, {"tile_rows": 8}):
+        print(f"[random small] {dtype} {m}x{n} {kw}", flush=True)
+        Xg, res, mu, nu = _run(ctx, inst, dtype, K, **kw)
+        assert res["iters"] == K
+        assert _rel_max(Xg, R.X) <= tx
+        assert _rel_max(mu, R.mu) <= td and _rel_max(nu, R.nu) <= td
+
+
 @pytest.mark.parametrize("check_every", [1, 7, 0])
 def test_small_path_launch_chunks_and_stop(ctx, check_every):
     """The one-workgroup path runs up to 4096 iterations per launch and stops
