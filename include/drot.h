@@ -145,7 +145,9 @@ typedef struct {
 typedef struct {
   int64_t iters;          /* iterations executed (K; X holds X_K) */
   int32_t status;         /* DROT_OK or DROT_MAXITER (or the error code) */
-  int32_t reserved;
+  int32_t path;           /* how the iterations ran: 0 = sweep and aux launches
+                             (always in drot_solve_batched), 1 = the one-workgroup
+                             path (drot_params) */
   double objective;       /* <C, X_K>, accumulated in FP64 over the returned X */
   double dual_objective;  /* p.mu + q.nu at the returned duals */
   double r_primal, r_dual, gap;          /* exact, at the returned (X, mu, nu) */

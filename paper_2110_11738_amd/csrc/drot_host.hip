@@ -851,6 +851,7 @@ int drot_finish(drot_ctx* c, double* mu, double* nu, drot_result* out, void* str
   memset(out, 0, sizeof(*out));
   out->iters = h->iter;
   out->status = h->done ? h->status : DROT_MAXITER;
+  out->path = c->small ? 1 : 0;
   out->objective = h->f_pobj;
   out->dual_objective = h->f_dobj;
   out->r_primal = h->f_rp;

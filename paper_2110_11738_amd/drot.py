@@ -48,7 +48,7 @@ class Params(ctypes.Structure):
 
 class Result(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int64), ("status", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("objective", ctypes.c_double),
+                ("path", ctypes.c_int32), ("objective", ctypes.c_double),
                 ("dual_objective", ctypes.c_double), ("r_primal", ctypes.c_double),
                 ("r_dual", ctypes.c_double), ("gap", ctypes.c_double),
                 ("eps_primal", ctypes.c_double), ("eps_dual", ctypes.c_double),

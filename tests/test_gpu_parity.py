@@ -61,6 +61,15 @@ def _rel_max(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
+def _small_fits(dtype, m, n):
+    """The one-workgroup path's shape rule (a power-of-two number of 64-column
+    groups up to 8, and 16 rows per 32 float32 or 16 float64 entries a thread
+    holds)."""
+    cols = next((c for c in (1, 2, 4, 8) if n <= 64 * c), 0)
+    slots = 32 if dtype == "float32" else 16
+    return cols > 0 and m <= 16 * (slots // cols)
+
+
 # With the default parameters the one-workgroup path takes the first ten
 # shapes in float32 and the first eight in float64 (512 x 64
 # and 64 x 512 are its float32 row and column limits, 256 x 64 and 32 x 512
@@ -81,6 +90,7 @@ def test_trajectory_parity(ctx, dtype, m, n):
         R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=K, trace=True)
         tx, td, to = TOL[dtype]
         assert res["iters"] == K
+        assert res["path"] == (1 if _small_fits(dtype, m, n) else 0)
         ex = _rel_max(Xg, R.X)
         emu = _rel_max(mu, R.mu)
         enu = _rel_max(nu, R.nu)
@@ -107,22 +117,13 @@ def test_small_shapes_on_tiled_path(ctx, dtype, m, n):
     K = 25
     R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=K, trace=True)
     tx, td, to = TOL[dtype]
-    for kw in ({}, {"tile_rows": 16}):
+    for kw, path in (({}, 1), ({"tile_rows": 16}, 0)):
         print(f"[small/tiled] {dtype} {m}x{n} {kw}", flush=True)
         Xg, res, mu, nu = _run(ctx, inst, dtype, K, **kw)
-        assert res["iters"] == K
+        assert res["iters"] == K and res["path"] == path
         assert _rel_max(Xg, R.X) <= tx
         assert _rel_max(mu, R.mu) <= td and _rel_max(nu, R.nu) <= td
         assert abs(res["objective"] - R.info["pobj"]) <= to * abs(R.info["pobj"])
-
-
-def _small_fits(dtype, m, n):
-    """The one-workgroup path's shape rule (a power-of-two number of 64-column
-    groups up to 8, and 16 rows per 32 float32 or 16 float64 entries a thread
-    holds)."""
-    cols = next((c for c in (1, 2, 4, 8) if n <= 64 * c), 0)
-    slots = 32 if dtype == "float32" else 16
-    return cols > 0 and m <= 16 * (slots // cols)
 
 
 _RNG_SHAPES = np.random.default_rng(2024)
@@ -142,10 +143,10 @@ def test_random_small_shapes_follow_oracle(ctx, dtype, m, n):
     K = 15
     R = ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=K)
     tx, td, to = TOL[dtype]
-    for kw in ({}, {"tile_rows": 8}):
+    for kw, path in (({}, 1), ({"tile_rows": 8}, 0)):
         print(f"[random small] {dtype} {m}x{n} {kw}", flush=True)
         Xg, res, mu, nu = _run(ctx, inst, dtype, K, **kw)
-        assert res["iters"] == K
+        assert res["iters"] == K and res["path"] == path
         assert _rel_max(Xg, R.X) <= tx
         assert _rel_max(mu, R.mu) <= td and _rel_max(nu, R.nu) <= td
 
