@@ -49,6 +49,8 @@ __all__ = [
     "rho_runtime",
     "rho_accuracy",
     "config_batch",
+    "batch_problem",
+    "batch_shape",
     "grid_cost",
     "grid_histogram_pair",
 ]
@@ -289,23 +291,32 @@ def round_to(inst: Instance, dtype) -> Instance:
     return out
 
 
+def batch_problem(b: int, lo: int = 64, hi: int = 2048, seed: int = 0) -> Instance:
+    """Problem b of the ragged batch: m and n each uniform in [lo, hi]; each
+    side a 2-D cloud of 1-5 Gaussian blobs (sigma 0.1, means uniform in
+    [0,1]^2); squared-Euclidean cost normalised to max 1; Dirichlet(1)
+    marginals; rho0 = 1/ln m; tol 1e-4.  Every problem has its own seed."""
+    rng = np.random.default_rng([4, seed, b])
+    m = int(rng.integers(lo, hi + 1))
+    n = int(rng.integers(lo, hi + 1))
+    xs = gaussian_mixture_points(rng, m, 2, int(rng.integers(1, 6)), 0.1)
+    xt = gaussian_mixture_points(rng, n, 2, int(rng.integers(1, 6)), 0.1)
+    C, sc = sq_euclid_cost(xs, xt)
+    p = dirichlet1(rng, m)
+    q = dirichlet1(rng, n)
+    return Instance(C, p, q, rho_runtime(m, n), 1e-4, f"batch[{seed},{b}:{m}x{n}]", xs, xt, sc)
+
+
+def batch_shape(b: int, lo: int = 64, hi: int = 2048, seed: int = 0) -> tuple[int, int]:
+    """(m, n) of batch_problem(b) without building it."""
+    rng = np.random.default_rng([4, seed, b])
+    m = int(rng.integers(lo, hi + 1))
+    return m, int(rng.integers(lo, hi + 1))
+
+
 def config_batch(count: int = 512, lo: int = 64, hi: int = 2048, seed: int = 0) -> list:
-    """Ragged batch: m and n each uniform in [lo, hi]; each side a 2-D cloud of
-    1-5 Gaussian blobs (sigma 0.1, means uniform in [0,1]^2); squared-Euclidean
-    cost normalised to max 1; Dirichlet(1) marginals; rho0 = 1/ln m; tol 1e-4."""
-    out = []
-    for b in range(count):
-        rng = np.random.default_rng([4, seed, b])
-        m = int(rng.integers(lo, hi + 1))
-        n = int(rng.integers(lo, hi + 1))
-        xs = gaussian_mixture_points(rng, m, 2, int(rng.integers(1, 6)), 0.1)
-        xt = gaussian_mixture_points(rng, n, 2, int(rng.integers(1, 6)), 0.1)
-        C, sc = sq_euclid_cost(xs, xt)
-        p = dirichlet1(rng, m)
-        q = dirichlet1(rng, n)
-        out.append(Instance(C, p, q, rho_runtime(m, n), 1e-4, f"batch[{seed},{b}:{m}x{n}]",
-                            xs, xt, sc))
-    return out
+    """The ragged batch: batch_problem(b) for b < count."""
+    return [batch_problem(b, lo, hi, seed) for b in range(count)]
 
 
 GRID = 32

@@ -1,4 +1,5 @@
-"""Build the oracle's C library (oracle/libdrot_ref.so) with gcc.
+"""Build the oracle's C library (oracle/libdrot_ref.so: the FP64 DROT of
+drot_ref.c and the network simplex of netsimplex.c) with gcc.
 
 Test infrastructure: compiled by the package build step so that the tests
 and the CPU-baseline leg of the benchmark find it; nothing in the GPU path
@@ -9,13 +10,13 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "drot_ref.c")
+SRCS = [os.path.join(HERE, "drot_ref.c"), os.path.join(HERE, "netsimplex.c")]
 LIB = os.path.join(HERE, "libdrot_ref.so")
 
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-           "-shared", "-Wall", "-Wextra", "-o", LIB + ".tmp", SRC, "-lm"]
+           "-shared", "-Wall", "-Wextra", "-o", LIB + ".tmp", *SRCS, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

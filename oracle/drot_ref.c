@@ -13,7 +13,7 @@
  *     alpha) and the three accumulator updates, in that order.
  *   - The stopping criteria of Section 3 ("Stopping criteria"): r_primal,
  *     r_dual and the duality gap, with the implicit dual variables
- *     mu = phi/rho and nu = varphi/rho (eq. dual:var in Appendix B).
+ *     mu = phi/rho and nu = varphi/rho (eq. dual:var in Appendix A).
  *
  * Notation: the paper's row shift is phi (length m) and its column shift is
  * varphi (length n); here the column shift is called psi.  X is stored

@@ -1,12 +1,22 @@
-"""FP64 reference of the warm-start MLP (test infrastructure only).
+"""FP64 reference of the warm-start MLP (test infrastructure only: only the
+tests, the smoke check and the benchmark's CPU leg use it; the library never
+imports it).
 
 Network in -> hidden (ReLU) -> hidden (ReLU) -> out with mean-squared-error
 loss; flat parameters [W1, b1, W2, b2, W3, b3], W_l stored out_l x in_l.
-With `bf16=True` the values entering every matrix product (inputs, weights,
-activations, back-propagated gradients) are rounded to bfloat16 exactly where
-the GPU kernels round them, and everything else runs in float64; with
-`bf16=False` it is the plain network, whose gradient is pinned by finite
-differences in the tests.
+
+`bf16=True` is the network of the warm-start configuration, a bfloat16 network
+with float32 accumulation: every matrix product takes bfloat16 operands (the
+input, the weights, the activations of the forward pass and the gradients
+propagated back through the products), so those operands are rounded to the
+nearest bfloat16 (ties to even) and the products and everything else are
+evaluated in float64.  Biases, the ReLU masks, the loss and the bias gradients
+use the unrounded values.  `bf16=False` is the plain network, whose gradient
+is pinned by finite differences in the tests; on data for which every rounded
+operand is already a bfloat16 value the two modes agree exactly.
+
+`adam_step` is the Adam update (Kingma and Ba, "Adam: a method for
+stochastic optimization", 2015, Algorithm 1) in float64.
 """
 from __future__ import annotations
 
@@ -68,3 +78,18 @@ def forward(theta, x, dims, bf16: bool = True):
     a1 = np.maximum(r(x) @ r(W1).T + b1, 0.0)
     a2 = np.maximum(r(a1) @ r(W2).T + b2, 0.0)
     return r(a2) @ r(W3).T + b3
+
+
+def adam_step(theta, grad, m, v, step: int, lr: float, beta1: float = 0.9,
+              beta2: float = 0.999, eps: float = 1e-8):
+    """One Adam step on flat float64 arrays; `step` counts from 1.  Returns
+    (theta, m, v) after the step: biased first and second moment estimates,
+    their bias corrections by 1 - beta^step, and the update
+    lr * m_hat / (sqrt(v_hat) + eps)."""
+    theta = np.asarray(theta, dtype=np.float64)
+    g = np.asarray(grad, dtype=np.float64)
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** step)
+    v_hat = v / (1.0 - beta2 ** step)
+    return theta - lr * m_hat / (np.sqrt(v_hat) + eps), m, v

@@ -26,8 +26,9 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
+    srcs = [os.path.join(_HERE, f) for f in ("drot_ref.c", "netsimplex.c")]
     if not os.path.exists(_LIB_PATH) or (
-            os.path.getmtime(_LIB_PATH) < os.path.getmtime(os.path.join(_HERE, "drot_ref.c"))):
+            os.path.getmtime(_LIB_PATH) < max(os.path.getmtime(f) for f in srcs)):
         from . import build as _b
         _b.build()
     lib = ctypes.CDLL(_LIB_PATH)
@@ -40,6 +41,10 @@ def _load():
     lib.drot_ref_eval.argtypes = [ctypes.c_longlong, ctypes.c_longlong, _dp, _dp, _dp,
                                   ctypes.c_double, _dp, _dp, _dp, _dp]
     lib.drot_ref_info_len.restype = ctypes.c_int
+    lib.drot_ref_netsimplex.restype = ctypes.c_int
+    lib.drot_ref_netsimplex.argtypes = [
+        ctypes.c_longlong, ctypes.c_longlong, _dp, _dp, _dp, ctypes.c_double, ctypes.c_longlong,
+        _dp, _dp, _dp, _dp, ctypes.POINTER(ctypes.c_longlong)]
     _lib = lib
     return lib
 

@@ -5,7 +5,7 @@ fixed by the paper or by mathematics: the generic least-squares projection
 (Lemma 2), the literal three-matrix DR iteration (Section 3), exact optima
 (brute force, HiGHS, the monotone 1-D coupling, one-row/one-column and
 separable problems), the identities of the variational-representation lemma
-(Appendix B) and the optimality conditions of Proposition 1.
+(Appendix A) and the optimality conditions of Proposition 1.
 """
 import json
 import os
@@ -167,6 +167,51 @@ def test_separable_cost():
     assert abs(R.info["pobj"] - opt) / opt < 1e-8
 
 
+# --------------------------------------------------------------------------
+# Network simplex (oracle/netsimplex.c): exact optima for large instances
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("m,n,zeros", [(1, 1, False), (1, 9, False), (8, 1, False), (2, 2, False),
+                                       (7, 5, True), (30, 40, False), (45, 30, True),
+                                       (120, 90, False)])
+def test_network_simplex_equals_highs(m, n, zeros):
+    rng = np.random.default_rng([400, m, n, int(zeros)])
+    C, p, q = _rand_problem(rng, m, n, zeros)
+    r = exact.network_simplex(C, p, q)
+    opt_h = exact.lp_highs(C, p, q)[0]
+    X = r["X"]
+    assert abs(r["opt"] - opt_h) <= 1e-12 * max(abs(opt_h), 1e-300) + 1e-15
+    assert X.min() >= 0.0
+    np.testing.assert_array_equal(X.sum(axis=1), p)  # dyadic marginals: exact flows
+    np.testing.assert_array_equal(X.sum(axis=0), q)
+    assert abs(float((C * X).sum()) - r["opt"]) <= 1e-14
+    assert r["lb"] <= r["ub"] + 1e-14 and r["ub"] - r["lb"] <= 1e-12
+
+
+@pytest.mark.parametrize("n", [3, 6, 8])
+def test_network_simplex_equals_brute_force(n):
+    for seed in range(3):
+        inst = assignment_instance(seed, n)
+        r = exact.network_simplex(inst.C, inst.p, inst.q)
+        assert abs(r["opt"] - exact.brute_force_uniform(inst.C)) <= 1e-15
+
+
+def test_network_simplex_closed_forms():
+    # points on a line: the monotone coupling (closed form)
+    inst = line_instance(3, 700, 900)
+    opt_line, _ = exact.line_monotone(inst.xs, inst.xt, inst.C, inst.p, inst.q)
+    assert abs(exact.network_simplex(inst.C, inst.p, inst.q)["opt"] - opt_line) <= 1e-13 * opt_line
+    # separable costs: every feasible plan costs g.p + h.q
+    sep = separable_instance(2, 60, 80)
+    opt_sep = exact.separable(sep.meta["g"], sep.meta["h"], sep.p, sep.q)
+    assert abs(exact.network_simplex(sep.C, sep.p, sep.q)["opt"] - opt_sep) <= 1e-14
+    # one row / one column: the only feasible plan
+    rng = np.random.default_rng(401)
+    C, p, q = _rand_problem(rng, 1, 13)
+    assert abs(exact.network_simplex(C, p, q)["opt"] - exact.single_row(C, q)) <= 1e-15
+    C, p, q = _rand_problem(rng, 11, 1)
+    assert abs(exact.network_simplex(C, p, q)["opt"] - exact.single_col(C, p)) <= 1e-15
+
+
 def test_hand_solved_two_by_two():
     """C = [[1,3],[2,5]], p = (0.4,0.6), q = (0.7,0.3).  Feasible plans are
     [[a, .4-a], [.7-a, a-.1]] with a in [.1,.4] and cost a + 2.1, so the
@@ -180,7 +225,7 @@ def test_hand_solved_two_by_two():
 
 
 # --------------------------------------------------------------------------
-# Appendix B (variational representation) and Proposition 1
+# Appendix A (variational representation) and Proposition 1
 # --------------------------------------------------------------------------
 def test_variational_identities_each_iteration():
     """For every k: <C,X_{k+1}> - p.mu_{k+1} - q.nu_{k+1} = -<Y_{k+1}, Y_{k+1}-Y_k>/rho,
@@ -296,6 +341,65 @@ def test_mlp_reference_gradient_matches_finite_differences():
                  - mlp_ref.loss_and_grad(theta - e, x, t, dims, bf16=False)[0]) / (2 * h)
     np.testing.assert_allclose(g, fd, rtol=1e-6, atol=1e-8)
     assert abs(loss - ((mlp_ref.forward(theta, x, dims, bf16=False) - t) ** 2).mean()) < 1e-15
+
+
+def test_mlp_bf16_mode_equals_plain_network_on_bfloat16_exact_data():
+    """Integer inputs and weights in {-2..2} and {-1, 0, 1}, integer biases
+    and targets, batch 2 x 2 outputs (the loss divides by 4): every operand
+    that the bfloat16 network rounds (inputs, weights, activations, the
+    back-propagated gradients) is a small integer or half-integer, already a
+    bfloat16 value, so the bfloat16 mode must equal the plain network exactly
+    -- a dropped or misplaced term in either mode breaks this."""
+    from oracle import mlp_ref
+    rng = np.random.default_rng(8)
+    dims = (2, 2, 2)
+    n_par = 2 * 2 + 2 + 2 * 2 + 2 + 2 * 2 + 2
+    for _ in range(20):
+        theta = rng.integers(-1, 2, n_par).astype(np.float64)
+        x = rng.integers(-2, 3, (2, 2)).astype(np.float64)
+        t = rng.integers(-3, 4, (2, 2)).astype(np.float64)
+        l16, g16 = mlp_ref.loss_and_grad(theta, x, t, dims, bf16=True)
+        l64, g64 = mlp_ref.loss_and_grad(theta, x, t, dims, bf16=False)
+        assert l16 == l64
+        np.testing.assert_array_equal(g16, g64)
+        np.testing.assert_array_equal(mlp_ref.forward(theta, x, dims, True),
+                                      mlp_ref.forward(theta, x, dims, False))
+
+
+def test_adam_two_steps_by_hand():
+    """theta_0 = 1, gradients 1/2 then -1/4, lr 0.1, eps 0.  By hand:
+    step 1: m = 1/20, v = 1/4000, m_hat = 1/2, v_hat = 1/4, theta_1 = 0.9;
+    step 2: m = 9/10 * 1/20 - 1/40 = 1/50, v = 999/1000 * 1/4000 + 1/16000 =
+    1249/4000000, m_hat = (1/50) / (1 - 0.81) = 2/19, v_hat = v / (1 - 0.998001)
+    = 1249/7996, theta_2 = 0.9 - 0.1 (2/19) / sqrt(1249/7996) = 0.87336629603..."""
+    from oracle import mlp_ref
+    th, m, v = np.array([1.0]), np.zeros(1), np.zeros(1)
+    th, m, v = mlp_ref.adam_step(th, [0.5], m, v, 1, 0.1, eps=0.0)
+    assert abs(th[0] - 0.9) < 1e-15 and abs(m[0] - 0.05) < 1e-16 and abs(v[0] - 2.5e-4) < 1e-18
+    th, m, v = mlp_ref.adam_step(th, [-0.25], m, v, 2, 0.1, eps=0.0)
+    assert abs(m[0] - 0.02) < 1e-16 and abs(v[0] - 1249 / 4e6) < 1e-18
+    assert abs(th[0] - (0.9 - 0.2 / 19 * np.sqrt(7996 / 1249))) < 1e-15
+    assert abs(th[0] - 0.8733662960339598) < 1e-14
+
+
+def test_adam_constant_gradient_moves_lr_per_step():
+    """With eps = 0 and the same gradient at every step, the bias corrections
+    make m_hat = g and v_hat = g^2 exactly, so each coordinate moves by lr in
+    the direction of -sign(g) per step whatever the gradient's magnitude; and
+    the update is invariant to scaling the gradient."""
+    from oracle import mlp_ref
+    g = np.array([3e-4, -2.0, 50.0, -7e-6])
+    th0 = np.array([0.5, -1.0, 2.0, 0.0])
+    th, m, v = th0.copy(), np.zeros(4), np.zeros(4)
+    ths, ms, vs = th0.copy(), np.zeros(4), np.zeros(4)
+    for k in range(1, 11):
+        th, m, v = mlp_ref.adam_step(th, g, m, v, k, 0.01, eps=0.0)
+        ths, ms, vs = mlp_ref.adam_step(ths, 1000.0 * g, ms, vs, k, 0.01, eps=0.0)
+        np.testing.assert_allclose(th, th0 - 0.01 * k * np.sign(g), rtol=0, atol=1e-13)
+        np.testing.assert_allclose(ths, th, rtol=0, atol=1e-13)
+    # eps bounds the step where the gradient is tiny: |update| <= lr |g| / eps
+    th, _, _ = mlp_ref.adam_step(np.zeros(1), [1e-12], np.zeros(1), np.zeros(1), 1, 0.01)
+    assert abs(th[0]) <= 0.01 * 1e-12 / 1e-8 * (1 + 1e-12)
 
 
 def test_bf16_rounding_reference():
