@@ -102,12 +102,20 @@ def pmc_traffic(m, n):
     return float(kv["sweep_traffic_bytes"])
 
 
+def graph_size(steps, check_every):
+    """Iterations per captured graph for a timed region of `steps`: the
+    largest divisor of `steps` not above `check_every`, so that the timed
+    region is whole graph replays."""
+    return max(d for d in range(1, max(1, min(steps, check_every)) + 1) if steps % d == 0)
+
+
 def timed_run(ctx, bind, steps, warmup, flags):
-    """Bind with `flags` (bind(flags, max_iter)), run `warmup` iterations,
-    then time exactly `steps`.  Returns (seconds, average sweep ms or None,
-    sweeps timed)."""
+    """Bind with `flags` (bind(flags, max_iter)), capture the graph, run
+    `warmup` iterations, then time exactly `steps`.  Returns (seconds,
+    average sweep ms or None, sweeps timed)."""
     import torch
     bind(flags, warmup + steps + 1)
+    ctx.iterate(0)  # graph capture, outside the timed region
     if warmup:
         ctx.iterate(warmup)
     torch.cuda.synchronize()
@@ -145,12 +153,13 @@ def dense_binder(ctx, C, p, q, rho, args, tile=None):
     rows, chunks, groups = tile if tile else (args.tile_rows, args.tile_chunks, args.tile_groups)
 
     def bind(flags, max_iter):
-        prm = drot.make_params(rho, 0.0, max_iter, check_every=args.check_every, flags=flags,
+        prm = drot.make_params(rho, 0.0, max_iter, check_every=bind.check_every, flags=flags,
                                tile_rows=rows, tile_chunks=chunks,
                                tile_unroll=args.tile_unroll, cache_mode=args.cache_mode,
                                tile_groups=groups)
         ctx.bind(C, p, q, X, prm)
     bind.X = X
+    bind.check_every = args.check_every
     return bind
 
 
@@ -274,12 +283,16 @@ def protocol_runs(ctx, bind, runs=10, iters=100):
         torch.cuda.synchronize()
         rates.append(iters / (time.perf_counter() - t0))
     r = sorted(rates)
-    # For 10 runs the order statistics 2 and 9 (1-based) bracket the median
-    # with 97.9% confidence (binomial, p = 1/2).
+    # Distribution-free confidence interval of the median: for 10 runs the
+    # order statistics 2 and 9 (1-based) bracket the population median with
+    # probability 1 - 2 P(Binomial(10, 1/2) <= 1) = 1 - 22/1024 = 97.9%
+    # (at least the 95% of the paper's protocol).
     lo, hi = (r[1], r[-2]) if runs >= 10 else (r[0], r[-1])
     log(f"protocol {runs}x{iters}: median {statistics.median(r):.1f} it/s [{lo:.1f}, {hi:.1f}]")
     return {"runs": runs, "iterations": iters, "median_iter_per_s": statistics.median(r),
-            "interval_iter_per_s": [lo, hi], "interval": "order statistics 2 and 9 of 10"}
+            "interval_iter_per_s": [lo, hi],
+            "interval": "distribution-free 97.9% confidence interval of the median: order "
+                        "statistics 2 and 9 of 10 (binomial, p = 1/2)"}
 
 
 def paper_sizes_section(ctx, sizes=(100, 200, 500, 1000, 2000, 5000, 10000, 20000), runs=10,
@@ -545,26 +558,45 @@ def tol_forms_section(ctx, rho0=2.0, tol=1e-4, n_seq=64):
     return out
 
 
-def cpu_baseline(inst, budget_s=20.0):
-    """Time the FP64 oracle per iteration on a bounded sample of iterations."""
-    import numpy as np
+def _oracle_rate(inst, parallel, budget_s):
+    """Iterations/s of the FP64 oracle on `inst` over a bounded sample:
+    (1 + k) iterations minus one, the initialisation time subtracted."""
+    from oracle import ref
+    t0 = time.perf_counter()
+    ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=1, parallel=parallel)
+    t_one = time.perf_counter() - t0
+    k = max(2, min(1000, int(budget_s / max(t_one / 2, 1e-3))))
+    t0 = time.perf_counter()
+    ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=1 + k, parallel=parallel)
+    t_k = time.perf_counter() - t0
+    return k / (t_k - t_one), k, t_k
+
+
+def cpu_baseline(inst, budget_s=10.0, gpu_iters_to_tol=None):
+    """The FP64 oracle (oracle/drot_ref.c) per iteration on the host cores:
+    its OpenMP build on every thread OMP_NUM_THREADS allows (the reported
+    value) and its one-thread build, each on a bounded sample."""
     from oracle import ref
     m, n = inst.m, inst.n
-    t0 = time.perf_counter()
-    ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=1)
-    t_one = time.perf_counter() - t0
-    k = max(2, int(budget_s / max(t_one / 2, 1e-3)))
-    k = min(k, 1000)
-    t0 = time.perf_counter()
-    ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=1 + k)
-    t_k = time.perf_counter() - t0
-    per_iter = (t_k - t_one) / k
-    del np
-    return {"value": 1.0 / per_iter, "unit": "iter/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle/drot_ref.c (FP64, single thread) on the same {m}x{n} instance "
-                      f"upcast from float32: ({1 + k} - 1) iterations from X0 = p q^T, "
-                      f"initialisation time subtracted; {t_k:.1f}s of CPU work",
-            "host_cpu": _cpu_model()}
+    rate, k, t_k = _oracle_rate(inst, True, budget_s)
+    rate1, k1, t_k1 = _oracle_rate(inst, False, budget_s)
+    threads = ref.threads(parallel=True)
+    out = {"value": rate, "unit": "iter/s", "cores": threads, "kind": "oracle",
+           "sample": f"oracle/drot_ref.c (FP64; OpenMP build, rows split over {threads} threads) "
+                     f"on the same {m}x{n} instance upcast from float32: ({1 + k} - 1) iterations "
+                     f"from X0 = p q^T, initialisation time subtracted; {t_k:.1f}s of CPU work",
+           "single_thread": {"value": rate1, "unit": "iter/s", "cores": 1,
+                             "sample": f"one-thread build, ({1 + k1} - 1) iterations, "
+                                       f"{t_k1:.1f}s"},
+           "host_cpu": _cpu_model(), "nproc": os.cpu_count(),
+           "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+           else None}
+    if gpu_iters_to_tol:
+        out["projected_time_to_tol_s"] = {
+            "value": gpu_iters_to_tol / rate, "label": "projected: GPU iterations to the 1e-4 "
+            "test at rho0 = 1/ln m divided by the all-core oracle rate (not run)",
+            "iters": gpu_iters_to_tol}
+    return out
 
 
 def _cpu_model():
@@ -599,8 +631,8 @@ def main():
     ap.add_argument("--no-skipc", action="store_true")
     ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuned runs")
-    ap.add_argument("--tol-large", action="store_true",
-                    help="also time the large instance to the 1e-4 test (minutes)")
+    ap.add_argument("--no-tol-large", action="store_true",
+                    help="skip timing the large instance to the 1e-4 test (about 3.5 minutes)")
     ap.add_argument("--tol-large-rho0", type=float, default=2.0)
     ap.add_argument("--tol-forms", action="store_true",
                     help="time to 1e-4 of the reduced-byte and batched forms against plain float32 "
@@ -637,15 +669,21 @@ def main():
         inst = make_instance(args.m, args.n)
         C, p, q = upload(inst)
         m, n = args.m, args.n
-        log(f"timing {args.steps} iterations after {args.warmup} warm-up iterations")
+        G = graph_size(args.steps, args.check_every)
+        log(f"timing {args.steps} iterations ({args.steps // G} replays of a {G}-iteration graph) "
+            f"after {args.warmup} warm-up iterations")
         bind = dense_binder(ctx, C, p, q, inst.rho, args)
+        bind.check_every = G
         r = measure(ctx, bind, args.steps, args.warmup)
+        bind.check_every = args.check_every
         secs, sweep_ms, cnt = r["seconds"], r["sweep_ms"], r["sweeps_timed"]
         value = args.steps / secs
         alg_bytes = BYTES_PER_ENTRY_F32 * m * n
         achieved = alg_bytes / (sweep_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "label": f"{m}x{n}: plan and cost (128 MiB) resident in the 256 MB last-level "
+                         f"cache, so not an HBM figure; the HBM roofline is the 20000^2 instance",
                 "kernel": "sweep_kernel<float,iter>", "bytes_per_launch": alg_bytes,
                 "traffic_bytes_per_launch": None,
                 "avg_launch_us": sweep_ms * 1e3, "launches_timed": cnt,
@@ -669,12 +707,16 @@ def main():
             "data": "synthetic",
             "config": {"workload": f"DROT mixture2d {m}x{n} float32 (two 2-D 5-Gaussian clouds, "
                                    f"sigma 0.1, sq-Euclidean C / max, Dirichlet(1) marginals, "
-                                   f"rho0 = 1/ln m)", "m": m, "n": n, "rho": inst.rho,
+                                   f"rho0 = 1/ln m); value = iterations/s at {m}x{n} (graph "
+                                   f"replays of {G} iterations); roofline = the sweep at "
+                                   f"{args.large}x{args.large} (the HBM instance)",
+                       "m": m, "n": n, "rho": inst.rho, "graph_iterations": G,
                        "tile_rows": args.tile_rows, "tile_chunks": args.tile_chunks,
                        "tile_unroll": args.tile_unroll, "cache_mode": args.cache_mode,
                        "tile_groups": args.tile_groups,
                        "check_every": args.check_every, "parallelism": "single GPU"},
             "roofline": roof,
+            "roofline_cache_resident": roof,
         }
 
         # ---- the paper's runtime protocol: 10 runs x 100 iterations -----------------
@@ -716,8 +758,11 @@ def main():
 
         # ---- CPU oracle baseline ----------------------------------------------------
         if not args.no_cpu:
-            out["cpu_baseline"] = cpu_baseline(inst)
-            log(f"cpu oracle {out['cpu_baseline']['value']:.3f} it/s")
+            gi = out.get("time_to_tol", {}).get("iters")
+            out["cpu_baseline"] = cpu_baseline(inst, gpu_iters_to_tol=gi)
+            log(f"cpu oracle {out['cpu_baseline']['value']:.3f} it/s on "
+                f"{out['cpu_baseline']['cores']} threads, "
+                f"{out['cpu_baseline']['single_thread']['value']:.3f} it/s on one")
 
     del C, p, q
     torch.cuda.empty_cache()
@@ -738,19 +783,27 @@ def main():
         ksteps, kwarm = 40, 5
         ab = BYTES_PER_ENTRY_F32 * L * L
         binder = dense_binder(ctx, C, p, q, rho_l, args)
+        binder.check_every = graph_size(ksteps, args.check_every)
         r = measure(ctx, binder, ksteps, kwarm)
         secs_l, sweep_l, cnt_l = r["seconds"], r["sweep_ms"], r["sweeps_timed"]
         ach = ab / (sweep_l * 1e-3) / 1e9
         tb_l = pmc_traffic(L, L)
+        roof_l = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                  "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                  "traffic": (tb_l / (sweep_l * 1e-3) / 1e9 if tb_l is not None else None),
+                  "kernel": "sweep_kernel<float,iter>",
+                  "workload": f"mixture2d {L}x{L} float32 (3.2 GB of plan and cost)",
+                  "bytes_per_launch": ab, "traffic_bytes_per_launch": tb_l,
+                  "avg_launch_us": sweep_l * 1e3, "launches_timed": cnt_l,
+                  "timing": "hipExtLaunchKernel start/stop events on every sweep of an eager "
+                            f"timed region of {ksteps} iterations",
+                  "iteration_GBs": ab / (secs_l / ksteps) / 1e9,
+                  "iteration_frac": ab / (secs_l / ksteps) / 1e9 / HBM_PEAK_GBS}
+        if tb_l is not None:
+            roof_l["traffic_source"] = os.path.relpath(pmc_summary(L, L), ROOT)
         out["large"] = {"m": L, "n": L, "iter_per_s": ksteps / secs_l,
-                        "ms_per_iter": 1e3 * secs_l / ksteps,
-                        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
-                                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                                     "traffic": (tb_l / (sweep_l * 1e-3) / 1e9
-                                                 if tb_l is not None else None),
-                                     "traffic_bytes_per_launch": tb_l,
-                                     "bytes_per_launch": ab, "avg_launch_us": sweep_l * 1e3,
-                                     "launches_timed": cnt_l}}
+                        "ms_per_iter": 1e3 * secs_l / ksteps, "roofline": roof_l}
+        out["roofline"] = roof_l
         log(f"{L}^2: {ksteps / secs_l:.1f} it/s, sweep {sweep_l * 1e3:.1f} us -> {ach:.0f} GB/s "
             f"({100 * ach / HBM_PEAK_GBS:.1f}% of peak)")
         if not args.no_tune:
@@ -764,7 +817,7 @@ def main():
                                      "frac": ach_t / HBM_PEAK_GBS}
             log(f"{L}^2 tuned: {ksteps / r['seconds']:.1f} it/s, sweep {r['sweep_ms'] * 1e3:.1f} us "
                 f"-> {ach_t:.0f} GB/s ({100 * ach_t / HBM_PEAK_GBS:.1f}% of peak)")
-        if args.tol_large:
+        if not args.no_tol_large:
             out["large"]["time_to_tol"] = time_to_tol_logged(ctx, C, p, q, args.tol_large_rho0,
                                                              args)
 

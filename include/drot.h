@@ -335,9 +335,16 @@ int drot_mlp_forward(drot_mlp *mlp, int batch, const float *x, float *y, void *s
  * the flat parameters (grad may be NULL). */
 int drot_mlp_gradients(drot_mlp *mlp, int batch, const float *x, const float *t, float *grad,
                        double *loss, void *stream);
-/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the batch's loss. */
+/* One Adam step (Kingma and Ba, 2015: beta1 0.9, beta2 0.999, eps 1e-8, bias
+ * corrections 1 - beta^k at the network's k-th step) on the batch's loss. */
 int drot_mlp_train_step(drot_mlp *mlp, int batch, const float *x, const float *t, float lr,
                         double *loss, void *stream);
+/* The same Adam step with a caller-supplied gradient `grad` (device float32,
+ * the flat parameter order, n_params entries; only read), e.g. gradients
+ * summed over several data-parallel replicas before the step.  Shares the
+ * step counter and moment estimates with drot_mlp_train_step.  lr > 0 and
+ * grad != NULL, else DROT_EINVAL. */
+int drot_mlp_apply_gradients(drot_mlp *mlp, const float *grad, float lr, void *stream);
 
 /* ---- checkpoint and resume (not in the paper; the iteration state of
  * Algorithm 1 is X plus the O(m+n) vectors and scalars listed there) ------- */

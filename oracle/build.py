@@ -12,15 +12,19 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRCS = [os.path.join(HERE, "drot_ref.c"), os.path.join(HERE, "netsimplex.c")]
 LIB = os.path.join(HERE, "libdrot_ref.so")
+# The same sources with OpenMP: the sweep's rows split over threads (used to
+# time the oracle on every core; one thread reproduces LIB's arithmetic).
+LIB_OMP = os.path.join(HERE, "libdrot_ref_omp.so")
 
 
 def build(verbose: bool = False) -> str:
-    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-           "-shared", "-Wall", "-Wextra", "-o", LIB + ".tmp", *SRCS, "-lm"]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
+    for lib, extra in ((LIB, []), (LIB_OMP, ["-fopenmp"])):
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+               "-shared", "-Wall", "-Wextra", *extra, "-o", lib + ".tmp", *SRCS, "-lm"]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        os.replace(lib + ".tmp", lib)
     return LIB
 
 

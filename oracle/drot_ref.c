@@ -30,10 +30,20 @@
  *   - Warm start: phi_0, psi_0 may be nonzero; then a_0 = Y_0 e - p and
  *     b_0 = Y_0^T f - q with Y_0 = X_0 + phi_0 e^T + f psi_0^T.
  * Compiled with -ffp-contract=off; every sum runs in a fixed order.
+ *
+ * Threads: built with -fopenmp (a second library, used only to time the
+ * oracle on every core) the row loop of the sweep is split into T contiguous
+ * row ranges, one per thread; each range keeps its own column sums and cost
+ * and r_dual sums in row order, and the T partials are added in range order.
+ * With one thread (the default build) this is exactly the row-major order of
+ * a single loop.
  */
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define REF_OK 0
 #define REF_MAXITER 1
@@ -49,6 +59,41 @@ enum {
 static double maxd(double a, double b) { return a > b ? a : b; }
 
 int drot_ref_info_len(void) { return I_NINFO; }
+
+/* Threads the sweep uses (1 without OpenMP). */
+int drot_ref_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* Step 4 and the sums of step 5 on rows [i0, i1): X_{k+1} written in place,
+ * row sums to u[i], column sums of these rows to v (n entries), and the
+ * partial <C, X_{k+1}> and r_dual^2 (at the incoming shifts) to out[0], out[1]. */
+static void sweep_rows(long long i0, long long i1, long long n, const double *C,
+                       const double *phi, const double *psi, double rho, double *X,
+                       double *u, double *v, double *out) {
+  double rd2 = 0.0, cost = 0.0;
+  for (long long j = 0; j < n; ++j) v[j] = 0.0;
+  for (long long i = i0; i < i1; ++i) {
+    u[i] = 0.0;
+    for (long long j = 0; j < n; ++j) {
+      const double c = C[i * n + j];
+      const double d = phi[i] / rho + psi[j] / rho - c;
+      if (d > 0) rd2 += d * d;
+      double x = X[i * n + j] + phi[i] + psi[j] - rho * c;
+      if (!(x > 0)) x = 0.0;
+      X[i * n + j] = x;
+      u[i] += x;
+      v[j] += x;
+      cost += c * x;
+    }
+  }
+  out[0] = cost;
+  out[1] = rd2;
+}
 
 /*
  * Run DROT for at most max_iter iterations.
@@ -75,10 +120,15 @@ int drot_ref_solve(long long m, long long n, const double *C, const double *p,
   double *u = malloc(sizeof(double) * m), *v = malloc(sizeof(double) * n);
   double *r = malloc(sizeof(double) * m), *s = malloc(sizeof(double) * n);
   double *phin = malloc(sizeof(double) * m), *psin = malloc(sizeof(double) * n);
-  if (!a || !b || !u || !v || !r || !s || !phin || !psin) {
+  const int T = drot_ref_threads();
+  double *vpart = malloc(sizeof(double) * (size_t)n * (size_t)T);
+  double *spart = malloc(sizeof(double) * 2 * (size_t)T);
+  if (!a || !b || !u || !v || !r || !s || !phin || !psin || !vpart || !spart) {
     free(a); free(b); free(u); free(v); free(r); free(s); free(phin); free(psin);
+    free(vpart); free(spart);
     return REF_ENOMEM;
   }
+  int nt = 1;
   const double mn = (double)(m + n);
 
   /* Step 1: X_0 (p q^T unless given) and the initial shifts. */
@@ -120,21 +170,25 @@ int drot_ref_solve(long long m, long long n, const double *C, const double *p,
     /* Step 4: X_{k+1} = [X_k + phi_k e^T + f psi_k^T - rho C]_+ ;
      * r_dual at (phi_k, psi_k) from the same read of C;
      * Step 5 sums u = X_{k+1} e, v = X_{k+1}^T f and <C, X_{k+1}>. */
-    double rd2 = 0.0, cost = 0.0;
-    for (long long i = 0; i < m; ++i) u[i] = 0.0;
+#ifdef _OPENMP
+#pragma omp parallel num_threads(T)
+    {
+      const int t = omp_get_thread_num(), tn = omp_get_num_threads();
+#pragma omp single
+      nt = tn;
+      sweep_rows(m * t / tn, m * (t + 1) / tn, n, C, phi, psi, rho, X, u,
+                 vpart + (size_t)t * (size_t)n, spart + 2 * t);
+    }
+#else
+    sweep_rows(0, m, n, C, phi, psi, rho, X, u, vpart, spart);
+#endif
+    double cost = 0.0, rd2 = 0.0;
     for (long long j = 0; j < n; ++j) v[j] = 0.0;
-    for (long long i = 0; i < m; ++i)
-      for (long long j = 0; j < n; ++j) {
-        const double c = C[i * n + j];
-        const double d = phi[i] / rho + psi[j] / rho - c;
-        if (d > 0) rd2 += d * d;
-        double x = X[i * n + j] + phi[i] + psi[j] - rho * c;
-        if (!(x > 0)) x = 0.0;
-        X[i * n + j] = x;
-        u[i] += x;
-        v[j] += x;
-        cost += c * x;
-      }
+    for (int t = 0; t < nt; ++t) {
+      for (long long j = 0; j < n; ++j) v[j] += vpart[(size_t)t * (size_t)n + j];
+      cost += spart[2 * t];
+      rd2 += spart[2 * t + 1];
+    }
     /* Step 5: residuals and beta. */
     double sr = 0.0, nr2 = 0.0, ns2 = 0.0;
     for (long long i = 0; i < m; ++i) {
@@ -201,6 +255,7 @@ int drot_ref_solve(long long m, long long n, const double *C, const double *p,
   info[I_NORMC] = normC;
   info[I_NORMPQ] = normpq;
   free(a); free(b); free(u); free(v); free(r); free(s); free(phin); free(psin);
+  free(vpart); free(spart);
   return status;
 }
 

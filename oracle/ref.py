@@ -13,7 +13,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libdrot_ref.so")
-_lib = None
+_LIB_OMP_PATH = os.path.join(_HERE, "libdrot_ref_omp.so")
+_libs = {}
 
 INFO_FIELDS = ["iters", "status", "pobj", "dobj", "r_primal", "r_dual", "gap",
                "eps_p", "eps_d", "eps_g", "alpha", "norm_c", "norm_pq"]
@@ -22,16 +23,18 @@ TRACE_FIELDS = ["pobj", "dobj", "r_primal", "r_dual_lag", "gap", "max_eps"]
 _dp = ctypes.POINTER(ctypes.c_double)
 
 
-def _load():
-    global _lib
-    if _lib is not None:
-        return _lib
+def _load(parallel: bool = False):
+    """The oracle library; parallel=True the OpenMP build of the same source
+    (rows of the sweep split over OMP_NUM_THREADS threads)."""
+    if parallel in _libs:
+        return _libs[parallel]
+    path = _LIB_OMP_PATH if parallel else _LIB_PATH
     srcs = [os.path.join(_HERE, f) for f in ("drot_ref.c", "netsimplex.c")]
-    if not os.path.exists(_LIB_PATH) or (
-            os.path.getmtime(_LIB_PATH) < max(os.path.getmtime(f) for f in srcs)):
+    if not os.path.exists(path) or (
+            os.path.getmtime(path) < max(os.path.getmtime(f) for f in srcs)):
         from . import build as _b
         _b.build()
-    lib = ctypes.CDLL(_LIB_PATH)
+    lib = ctypes.CDLL(path)
     lib.drot_ref_solve.restype = ctypes.c_int
     lib.drot_ref_solve.argtypes = [
         ctypes.c_longlong, ctypes.c_longlong, _dp, _dp, _dp, ctypes.c_double,
@@ -41,12 +44,18 @@ def _load():
     lib.drot_ref_eval.argtypes = [ctypes.c_longlong, ctypes.c_longlong, _dp, _dp, _dp,
                                   ctypes.c_double, _dp, _dp, _dp, _dp]
     lib.drot_ref_info_len.restype = ctypes.c_int
+    lib.drot_ref_threads.restype = ctypes.c_int
     lib.drot_ref_netsimplex.restype = ctypes.c_int
     lib.drot_ref_netsimplex.argtypes = [
         ctypes.c_longlong, ctypes.c_longlong, _dp, _dp, _dp, ctypes.c_double, ctypes.c_longlong,
         _dp, _dp, _dp, _dp, ctypes.POINTER(ctypes.c_longlong)]
-    _lib = lib
+    _libs[parallel] = lib
     return lib
+
+
+def threads(parallel: bool = False) -> int:
+    """Threads the sweep of the given build uses."""
+    return int(_load(parallel).drot_ref_threads())
 
 
 def _ptr(a):
@@ -83,14 +92,18 @@ class RefResult:
 
 
 def solve(C, p, q, rho: float, tol: float = 0.0, max_iter: int = 1000, tol_mode: int = 0,
-          X0=None, phi0=None, psi0=None, trace: bool = False) -> RefResult:
+          X0=None, phi0=None, psi0=None, trace: bool = False,
+          parallel: bool = False) -> RefResult:
     """Run FP64 DROT (Algorithm 1) until the stopping test or max_iter.
 
     X0=None starts from X_0 = p q^T.  phi0/psi0 are initial shifts in the
     paper's phi units (phi = rho * mu).  Returns X_K, phi_K, psi_K, a_K, b_K,
-    the info dict and (optionally) the per-iteration trace.
+    the info dict and (optionally) the per-iteration trace.  parallel=True
+    runs the OpenMP build (same steps; the column, cost and r_dual sums are
+    combined per row range, so results differ from the one-thread order only
+    by rounding).
     """
-    lib = _load()
+    lib = _load(parallel)
     C = _f64(C)
     m, n = C.shape
     p = _f64(p, (m,))

@@ -418,19 +418,38 @@ int drot_mlp_gradients(drot_mlp* n, int batch, const float* x, const float* t, f
   return DROT_OK;
 }
 
-int drot_mlp_train_step(drot_mlp* n, int batch, const float* x, const float* t, float lr,
-                        double* loss, void* stream) {
-  int rc = drot_mlp_gradients(n, batch, x, t, nullptr, loss, stream);
-  if (rc) return rc;
-  if (!(lr > 0.f)) return mfail(DROT_EINVAL, "lr must be positive");
-  hipStream_t s = (hipStream_t)stream;
+}  // extern "C"
+
+namespace {
+
+// One Adam step with the gradient in `g` (device, flat parameter order).
+int adam_step(drot_mlp* n, const float* g, float lr, hipStream_t s) {
   n->step += 1;
   const float b1 = 0.9f, b2 = 0.999f;
   const float c1 = 1.f - std::pow(b1, (float)n->step), c2 = 1.f - std::pow(b2, (float)n->step);
-  hipLaunchKernelGGL(adam, dim3(nblk(n->n_params)), dim3(256), 0, s, n->w, n->wb, n->g, n->m1,
+  hipLaunchKernelGGL(adam, dim3(nblk(n->n_params)), dim3(256), 0, s, n->w, n->wb, g, n->m1,
                      n->m2, n->n_params, lr, b1, b2, 1e-8f, c1, c2);
   MHIP(hipGetLastError());
   return DROT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int drot_mlp_train_step(drot_mlp* n, int batch, const float* x, const float* t, float lr,
+                        double* loss, void* stream) {
+  if (!(lr > 0.f)) return mfail(DROT_EINVAL, "lr must be positive");
+  int rc = drot_mlp_gradients(n, batch, x, t, nullptr, loss, stream);
+  if (rc) return rc;
+  return adam_step(n, n->g, lr, (hipStream_t)stream);
+}
+
+int drot_mlp_apply_gradients(drot_mlp* n, const float* grad, float lr, void* stream) {
+  if (!n || !grad) return mfail(DROT_EINVAL, "NULL argument");
+  if (!(lr > 0.f)) return mfail(DROT_EINVAL, "lr must be positive");
+  MHIP(hipSetDevice(n->device));
+  return adam_step(n, grad, lr, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -32,8 +32,8 @@ EXPORTED = ("drot_version", "drot_strerror", "drot_last_error", "drot_ctx_create
             "drot_finish", "drot_get_trace", "drot_bind_cost", "drot_solve_cost",
             "drot_solve_batched", "drot_mlp_create", "drot_mlp_destroy", "drot_mlp_num_params",
             "drot_mlp_set_weights", "drot_mlp_get_weights", "drot_mlp_forward",
-            "drot_mlp_gradients", "drot_mlp_train_step", "drot_tune", "drot_checkpoint_size",
-            "drot_checkpoint", "drot_resume")
+            "drot_mlp_gradients", "drot_mlp_train_step", "drot_mlp_apply_gradients", "drot_tune",
+            "drot_checkpoint_size", "drot_checkpoint", "drot_resume")
 
 
 class Params(ctypes.Structure):
@@ -122,6 +122,7 @@ def lib():
     L.drot_mlp_forward.argtypes = [vp, i32, vp, vp, vp]
     L.drot_mlp_gradients.argtypes = [vp, i32, vp, vp, vp, dp, vp]
     L.drot_mlp_train_step.argtypes = [vp, i32, vp, vp, ctypes.c_float, dp, vp]
+    L.drot_mlp_apply_gradients.argtypes = [vp, vp, ctypes.c_float, vp]
     L.drot_tune.argtypes = [vp, i64, ctypes.POINTER(Params), dp, vp]
     L.drot_checkpoint_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     L.drot_checkpoint.argtypes = [vp, vp, ctypes.c_size_t, vp]
@@ -426,6 +427,12 @@ class MLP:
         _check(lib().drot_mlp_gradients(self.handle, x.shape[0], _ptr(x), _ptr(t), _ptr(g),
                                         ctypes.byref(loss), _stream(stream)), allow=(OK,))
         return loss.value, g
+
+    def apply_gradients(self, grad, lr: float, stream=None) -> None:
+        if grad.numel() != self.n_params or grad.dtype.itemsize != 4 or not grad.is_contiguous():
+            raise ValueError("grad must be a contiguous float32 tensor of n_params entries")
+        _check(lib().drot_mlp_apply_gradients(self.handle, _ptr(grad), ctypes.c_float(lr),
+                                              _stream(stream)), allow=(OK,))
 
     def train_step(self, x, t, lr: float, stream=None) -> float:
         loss = ctypes.c_double()

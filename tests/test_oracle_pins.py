@@ -408,3 +408,21 @@ def test_bf16_rounding_reference():
     vals = np.array([1.0, 1.0 + 2.0 ** -7, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -2.5, 0.0])
     out = mlp_ref.bf16_round(vals)
     np.testing.assert_array_equal(out, [1.0, 1.0 + 2.0 ** -7, 1.0, 1.0 + 2.0 ** -6, -2.5, 0.0])
+
+
+def test_openmp_build_agrees_with_one_thread():
+    """The OpenMP build of the oracle (rows split over threads, per-range
+    partial sums added in range order) follows the one-thread oracle to
+    rounding: 1e-12 relative on X_K, the shifts and every trace entry."""
+    from gen import config_mixture_2d
+    inst = config_mixture_2d(31, 301, 257)
+    K = 60
+    A = ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=K, trace=True)
+    B = ref.solve(inst.C, inst.p, inst.q, inst.rho, 0.0, max_iter=K, trace=True, parallel=True)
+    assert ref.threads() == 1 and ref.threads(parallel=True) >= 1
+    for a, b in ((A.X, B.X), (A.phi, B.phi), (A.psi, B.psi), (A.trace, B.trace)):
+        assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max()
+    # the stopping iteration is the same
+    A = ref.solve(inst.C, inst.p, inst.q, inst.rho, 1e-5, max_iter=200_000)
+    B = ref.solve(inst.C, inst.p, inst.q, inst.rho, 1e-5, max_iter=200_000, parallel=True)
+    assert A.info["iters"] == B.info["iters"]
