@@ -82,6 +82,12 @@ struct drot_ctx {
   // Small problems iterate in one workgroup (small_kernel) instead of
   // sweep + aux launches.
   bool small = false;
+  // Pending form of the iteration (fewer than kAuxSplitMin aux workgroups):
+  // the aux launch only publishes its sums and the next sweep takes the
+  // scalar steps; state records st[0] (committed, what the host reads) and
+  // st[1], sum buffers bp[0] and bp[1], used by step parity within a group.
+  bool pend = false;
+  double* bp[2] = {nullptr, nullptr};
 
   // Iterations enqueued since bind (the skip-C schedule alternates by parity).
   bool skipc = false;
@@ -244,12 +250,13 @@ int validate(int64_t m, int64_t n, int dtype, const drot_cost* cost, const void*
   return DROT_OK;
 }
 
-int ensure_workspace(drot_ctx* c, int64_t m, int64_t n, const Geometry& g, size_t* offs) {
+// Offsets of the workspace's parts (offs[12]) and its total size.
+size_t workspace_layout(int64_t m, int64_t n, const Geometry& g, size_t* offs) {
   // st, trace, colpart, rowpart, tiles, a, b, phi64, psi64, phiT, psiT,
   // blockpart
   size_t o = 0;
   const size_t sizes[12] = {
-      sizeof(DevState),
+      2 * sizeof(DevState),
       sizeof(double) * kTraceCap * kTraceWidth,
       sizeof(double) * (size_t)g.g.n_rg * (size_t)g.g.ldcp,
       sizeof(double) * (size_t)g.g.n_ct * (size_t)m,
@@ -260,11 +267,16 @@ int ensure_workspace(drot_ctx* c, int64_t m, int64_t n, const Geometry& g, size_
       sizeof(double) * (size_t)n,
       sizeof(double) * (size_t)m,
       sizeof(double) * (size_t)n,
-      sizeof(double) * (size_t)aux_workgroups(m, n) * kSlots};
+      2 * sizeof(double) * (size_t)aux_workgroups(m, n) * kSlots};
   for (int k = 0; k < 12; ++k) {
     offs[k] = o;
     o += up(sizes[k]);
   }
+  return o;
+}
+
+int ensure_workspace(drot_ctx* c, int64_t m, int64_t n, const Geometry& g, size_t* offs) {
+  const size_t o = workspace_layout(m, n, g, offs);
   if (o <= c->ws_bytes) return DROT_OK;
   drop_graph(c);
   if (c->ws) {
@@ -290,11 +302,45 @@ int iter_mode(const drot_ctx* c, int64_t idx) {
   return (idx & 1) ? kIterB : kIterA;
 }
 
-// One iteration: sweep + aux.  With events (eager timing) the sweep's start
-// and end are the dispatch's own timestamps.
-int launch_iteration(drot_ctx* c, hipStream_t s, hipEvent_t e0, hipEvent_t e1, int mode) {
-  HIP_TRY(launch_sweep(c->dtype, mode, c->geo.tile, c->sa, s, e0, e1));
-  HIP_TRY(launch_aux(c->dtype, mode, c->sa, s, c->geo.tile.comp));
+// Kernel arguments of step j (0-based) of a group of iterations, whose first
+// iteration has global index `first` (iterations enqueued since bind).  A
+// group starts from the committed state in st[0].  Pending form: step j's
+// sweep closes iteration j - 1 from (st[(j-1)&1], bp[(j-1)&1]) and commits
+// st[j&1]; step j's aux reads st[j&1] and publishes into bp[j&1]; so no
+// kernel writes a record or buffer that another of its workgroups reads.
+SweepArgs step_args(const drot_ctx* c, int j, int64_t first) {
+  SweepArgs a = c->sa;
+  if (!c->pend) return a;
+  const int cur = j & 1;
+  a.st = c->st + cur;
+  a.blockpart = c->bp[cur];
+  if (j > 0) {
+    a.st_prev = c->st + (1 - cur);
+    a.bp_prev = c->bp[1 - cur];
+    a.prev_b = iter_mode(c, first + j - 1) == kIterB ? 1 : 0;
+  }
+  return a;
+}
+
+// The finishing launch of a group of k >= 1 steps (pending form): closes the
+// group's last iteration into st[0].
+int launch_group_end(drot_ctx* c, hipStream_t s, int k, int64_t first) {
+  if (!c->pend || k < 1) return DROT_OK;
+  SweepArgs a = c->sa;
+  a.st_prev = c->st + ((k - 1) & 1);
+  a.bp_prev = c->bp[(k - 1) & 1];
+  HIP_TRY(launch_finish(iter_mode(c, first + k - 1), a, s));
+  return DROT_OK;
+}
+
+// Step j of a group: sweep + aux.  With events (eager timing) the sweep's
+// start and end are the dispatch's own timestamps.
+int launch_iteration(drot_ctx* c, hipStream_t s, hipEvent_t e0, hipEvent_t e1, int j,
+                     int64_t first) {
+  const int mode = iter_mode(c, first + j);
+  const SweepArgs a = step_args(c, j, first);
+  HIP_TRY(launch_sweep(c->dtype, mode, c->geo.tile, a, s, e0, e1));
+  HIP_TRY(launch_aux(c->dtype, mode, a, s, c->geo.tile.comp, c->pend));
   return DROT_OK;
 }
 
@@ -315,11 +361,16 @@ int ensure_events(drot_ctx* c, int count) {
   return DROT_OK;
 }
 
-// Capture one launch (the sweep or the aux kernel) into a one-node graph.
-int capture_one(drot_ctx* c, bool sweep, int mode, hipGraph_t* out) {
+// Capture one launch of step j of a group (kind 0: the sweep, 1: the aux
+// kernel, 2: the group's finishing launch after j + 1 steps) into a graph.
+int capture_one(drot_ctx* c, int kind, int j, int64_t first, hipGraph_t* out) {
   HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-  hipError_t e = sweep ? launch_sweep(c->dtype, mode, c->geo.tile, c->sa, c->cap_stream)
-                       : launch_aux(c->dtype, mode, c->sa, c->cap_stream, c->geo.tile.comp);
+  const int mode = iter_mode(c, first + j);
+  const SweepArgs a = step_args(c, j, first);
+  hipError_t e = hipSuccess;
+  if (kind == 0) e = launch_sweep(c->dtype, mode, c->geo.tile, a, c->cap_stream);
+  if (kind == 1) e = launch_aux(c->dtype, mode, a, c->cap_stream, c->geo.tile.comp, c->pend);
+  if (kind == 2 && launch_group_end(c, c->cap_stream, j + 1, first)) e = hipErrorInvalidValue;
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
   if (e != hipSuccess || e2 != hipSuccess) {
@@ -340,20 +391,23 @@ int timed_count(int G) { return std::min(2, G - timed_first(G)); }
 // Graph of G iterations with event-record nodes around the timed sweeps,
 // built node by node; the kernels enter as captured child graphs.
 int build_timed_graph(drot_ctx* c, int G, hipGraph_t* out) {
-  // Child graphs per parity: [0] C-reading (or plain) iteration, [1] C-free.
-  hipGraph_t gs[2] = {nullptr, nullptr}, ga[2] = {nullptr, nullptr}, g = nullptr;
-  const int kinds = c->skipc ? 2 : 1;
+  // Child graphs of the step kinds: the arguments of step k depend on k only
+  // through k == 0, the parity of k (the pending form's records, the skip-C
+  // schedule) and, for the finishing launch, the parity of G.
+  hipGraph_t gs[3] = {nullptr, nullptr, nullptr}, ga[3] = {nullptr, nullptr, nullptr};
+  hipGraph_t gf = nullptr, g = nullptr;
   int rc = DROT_OK;
-  for (int q = 0; q < kinds && !rc; ++q) {
-    rc = capture_one(c, true, iter_mode(c, q), &gs[q]);
-    if (!rc) rc = capture_one(c, false, iter_mode(c, q), &ga[q]);
+  for (int q = 0; q < 3 && q < G && !rc; ++q) {
+    rc = capture_one(c, 0, q, 0, &gs[q]);
+    if (!rc) rc = capture_one(c, 1, q, 0, &ga[q]);
   }
+  if (!rc && c->pend) rc = capture_one(c, 2, G - 1, 0, &gf);
   hipError_t e = hipSuccess;
   if (!rc) e = hipGraphCreate(&g, 0);
   hipGraphNode_t prev = nullptr;
   const int t0 = timed_first(G), tn = timed_count(G);
   for (int k = 0; k < G && !rc && e == hipSuccess; ++k) {
-    const int q = k % kinds;
+    const int q = k == 0 ? 0 : 2 - (k & 1);  // 0: first, 1: odd, 2: even step
     const bool timed = k >= t0 && k < t0 + tn;
     const int slot = k - t0;
     hipGraphNode_t e0 = nullptr, s = nullptr, e1 = nullptr, x = nullptr;
@@ -373,10 +427,15 @@ int build_timed_graph(drot_ctx* c, int G, hipGraph_t* out) {
     if (e == hipSuccess) e = hipGraphAddChildGraphNode(&x, g, dep, 1, ga[q]);
     prev = x;
   }
-  for (int q = 0; q < 2; ++q) {
+  if (!rc && e == hipSuccess && gf) {
+    hipGraphNode_t f = nullptr;
+    e = hipGraphAddChildGraphNode(&f, g, &prev, 1, gf);
+  }
+  for (int q = 0; q < 3; ++q) {
     if (gs[q]) (void)hipGraphDestroy(gs[q]);
     if (ga[q]) (void)hipGraphDestroy(ga[q]);
   }
+  if (gf) (void)hipGraphDestroy(gf);
   if (!rc && e != hipSuccess) rc = fail(DROT_EDEVICE, "timed graph: %s", hipGetErrorString(e));
   if (rc) {
     if (g) (void)hipGraphDestroy(g);
@@ -401,7 +460,8 @@ int ensure_graph(drot_ctx* c) {
     HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     int rc = DROT_OK;
     for (int k = 0; k < G && rc == DROT_OK; ++k)
-      rc = launch_iteration(c, c->cap_stream, nullptr, nullptr, iter_mode(c, k));
+      rc = launch_iteration(c, c->cap_stream, nullptr, nullptr, k, 0);
+    if (rc == DROT_OK) rc = launch_group_end(c, c->cap_stream, G, 0);
     hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
     if (rc != DROT_OK) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -562,6 +622,7 @@ int drot_bind_cost(drot_ctx* c, int64_t m, int64_t n, int dtype, const drot_cost
              prm->tile_rows == 0 && prm->tile_chunks == 0 && prm->tile_unroll == 0 &&
              prm->tile_groups == 0 && prm->cache_mode == DROT_CACHE_AUTO &&
              small_fits(dtype, m, n);
+  c->pend = !c->small && aux_workgroups(m, n) < kAuxSplitMin;
   c->enq = 0;
   c->sweep_ms = 0.0;
   c->sweep_n = 0;
@@ -589,6 +650,8 @@ int drot_bind_cost(drot_ctx* c, int64_t m, int64_t n, int dtype, const drot_cost
   sa.phiT = base + offs[9];
   sa.psiT = base + offs[10];
   sa.blockpart = reinterpret_cast<double*>(base + offs[11]);
+  c->bp[0] = sa.blockpart;
+  c->bp[1] = sa.blockpart + (size_t)aux_workgroups(m, n) * kSlots;
   sa.mu0 = mu0;
   sa.nu0 = nu0;
   sa.st = c->st;
@@ -655,12 +718,14 @@ int run_eager(drot_ctx* c, hipStream_t s, int64_t count) {
   while (done < count) {
     const int k = (int)std::min<int64_t>(G, count - done);
     if (timed && (rc = ensure_events(c, 2 * k))) return rc;
+    const int64_t first = c->enq;
     for (int t = 0; t < k; ++t) {
       if ((rc = launch_iteration(c, s, timed ? c->ev[2 * t] : nullptr,
-                                 timed ? c->ev[2 * t + 1] : nullptr, iter_mode(c, c->enq))))
+                                 timed ? c->ev[2 * t + 1] : nullptr, t, first)))
         return rc;
       ++c->enq;
     }
+    if ((rc = launch_group_end(c, s, k, first))) return rc;
     if (timed) {
       HIP_TRY(hipStreamSynchronize(s));
       if ((rc = harvest_events(c, k))) return rc;

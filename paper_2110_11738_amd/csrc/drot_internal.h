@@ -144,6 +144,15 @@ struct SweepArgs {
   void* rowpart;           // [n_ct][m]
   double* tiles;           // [n_rg * n_ct][kTileSlots], workgroup (g, ct) at g * n_ct + ct
   double* blockpart;       // [kSlots][aux workgroups] (slot-major)
+  // Pending form of the iteration (few aux workgroups; see drot_kernels.hip):
+  // the scalar steps that close the previous iteration run at the start of
+  // the sweep, from that iteration's state record `st_prev` and the aux sums
+  // `bp_prev`; workgroup 0 commits the result to `st`.  nullptr: `st`
+  // already holds the state entering the iteration.  A one-wave finishing
+  // launch reads the same pair (st_prev, bp_prev) and commits into `st`.
+  const DevState* st_prev;
+  const double* bp_prev;
+  int prev_b;              // the previous iteration was a C-free (kIterB) one
   double* trace;           // [trace_cap][kTraceWidth]
   int64_t trace_cap;       // records kept (ring)
   double wall_rate;        // wall_clock64 ticks per second
@@ -168,7 +177,13 @@ struct TileCfg {
 hipError_t launch_sweep(int dtype, int mode, const TileCfg& t, const SweepArgs& a,
                         hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // `wide`: the float32 iteration's partials are float64 (compensated sweep).
-hipError_t launch_aux(int dtype, int mode, const SweepArgs& a, hipStream_t s, bool wide = false);
+// `publish`: the aux workgroups only publish their sums (pending form of the
+// iteration); the scalar steps run in the next sweep or in launch_finish.
+hipError_t launch_aux(int dtype, int mode, const SweepArgs& a, hipStream_t s, bool wide = false,
+                      bool publish = false);
+// One wave: the scalar steps of an iteration of mode `mode` from
+// (a.st_prev, a.bp_prev), committed to a.st.
+hipError_t launch_finish(int mode, const SweepArgs& a, hipStream_t s);
 hipError_t launch_prep(const SweepArgs& a, hipStream_t s);
 // `iters` iterations of a small problem in one one-workgroup launch.
 hipError_t launch_small(int dtype, const SweepArgs& a, int64_t iters, hipStream_t s);

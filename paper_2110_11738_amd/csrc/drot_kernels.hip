@@ -276,16 +276,147 @@ __device__ __forceinline__ StateIn load_state(const DevState* st) {
   return v;
 }
 
-// Run by wave 0 of the last aux workgroup (all lanes active): fixed-order sum
-// of all workgroups' scalar partials, then, in lane 0, the scalar steps of the
-// iteration (or of the initialisation or the final evaluation).  `blockpart`
-// is slot-major ([kSlots][nb]); in the iteration a column workgroup fills only
-// the column and tile slots and a row workgroup the row and tile slots, and
-// the sum skips the others.
+// The eight sums that close an iteration -- sum r, sum r^2, sum p phi~,
+// sum s, sum s^2, sum q psi~, <C, X> and sum [t]_+^2 -- from the aux
+// workgroups' published partials `bp` (slot-major [kSlots][nb]): each lane
+// adds a fixed subset in a fixed order, then a DPP reduction; every lane of
+// the wave gets the totals.  A column workgroup fills only the column and
+// tile slots and a row workgroup the row and tile slots, and the sum skips
+// the others.  AGENT: the sums were published by workgroups of the same
+// launch (device-scope loads after the acquire fence); otherwise by an
+// earlier launch, whose end made them visible to plain (cached) loads.
+template <bool AGENT>
+__device__ __forceinline__ void iter_sums(const double* bp, int nb, int col_wgs, double (&w)[8]) {
+  constexpr int B = 4;  // workgroups per lane in flight
+  const int lane = threadIdx.x & (kWave - 1);
+  constexpr int slot[8] = {kSR, kSR2, kSPphi, kSS, kSS2, kSQpsi, kST0, kST1};
+#pragma unroll
+  for (int s = 0; s < 8; ++s) w[s] = 0.0;
+  for (int k0 = 0; k0 < nb; k0 += B * kWave) {
+    double v[B][8];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int k = k0 + u * kWave + lane;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        bool use = k < nb;
+        if (s < 3) use = use && k >= col_wgs;
+        else if (s < 6) use = use && k < col_wgs;
+        const double* ptr = bp + (int64_t)slot[s] * nb + k;
+        v[u][s] = use ? (AGENT ? load_agent(ptr) : *ptr) : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+#pragma unroll
+      for (int s = 0; s < 8; ++s) w[s] += v[u][s];
+  }
+  wave_sum_n(w);
+}
+
+// The scalar steps closing iteration k = sv.iter + 1 (Algorithm 1 steps
+// 5-8, scalar part, and the stopping criteria of Section 3) from the sums w
+// of iter_sums and the state sv entering it: beta = f^T r / (m+n), the common
+// scalar part 2 beta - alpha of the new shifts, alpha <- alpha - beta, the
+// objectives, residuals and the test.  `nc`: the iteration read no C (the
+// C-free step of the skip-C schedule), so it has no <C,X> and no dual
+// residual: it records NaN for them and can only stop at max_iter.
+struct ScalarStep {
+  double cphi, cpsi, alpha, pobj, dobj, rp, rd, gap, test;
+  int64_t k;
+  int done, status;
+};
+
+__device__ __forceinline__ ScalarStep scalar_step(const StateIn& sv, const double (&w)[8],
+                                                  int64_t m, int64_t n, bool nc) {
+  ScalarStep f;
+  const double mn = (double)(m + n);
+  const double rho = sv.rho;
+  const double beta = w[0] / mn;
+  const double cc = 2.0 * beta - sv.alpha;
+  f.cphi = cc / (double)n;
+  f.cpsi = cc / (double)m;
+  f.alpha = sv.alpha - beta;
+  const double nan = __builtin_nan("");
+  f.pobj = nc ? nan : w[6];
+  f.dobj = (w[2] + f.cphi * sv.sum_p + w[5] + f.cpsi * sv.sum_q) / rho;
+  f.gap = fabs(f.pobj - f.dobj);
+  f.rp = sqrt(w[1] + w[4]);
+  f.rd = nc ? nan : sqrt(w[7]) / rho;
+  const double ep = f.rp / fmax(sv.norm_pq, 1e-300);
+  const double ed = f.rd / fmax(sv.norm_c, 1e-300);
+  const double eg = f.gap / fmax(fmax(fabs(f.pobj), fabs(f.dobj)), 1e-300);
+  f.test = sv.tol_mode ? fmax(f.rp, fmax(f.rd, f.gap)) : fmax(ep, fmax(ed, eg));
+  f.k = sv.iter + 1;
+  f.done = 0;
+  f.status = 0;
+  if ((!nc && !finite_d(f.test)) || !finite_d(f.alpha) || !finite_d(cc) || !finite_d(f.rp)) {
+    f.done = 1;
+    f.status = -3;
+  } else if (!nc && f.test <= sv.tol) {
+    f.done = 1;
+  } else if (f.k >= sv.max_iter) {
+    f.done = 1;
+    f.status = 1;
+  }
+  return f;
+}
+
+// Write the state after iteration f.k into `dst` (a copy of `src`, the
+// record entering it, with the iteration fields replaced) and its trace
+// record.  One thread.
+__device__ __forceinline__ void commit_step(DevState* dst, const DevState* src,
+                                            const ScalarStep& f, const SweepArgs& a,
+                                            uint64_t t_start) {
+  const uint64_t now = wall_clock64();
+  if (dst != src) *dst = *src;
+  dst->alpha = f.alpha;
+  dst->cphi = f.cphi;
+  dst->cpsi = f.cpsi;
+  dst->iter = f.k;
+  dst->t_last = now;
+  dst->pobj = f.pobj;
+  dst->dobj = f.dobj;
+  dst->rp = f.rp;
+  dst->rd = f.rd;
+  dst->gap = f.gap;
+  dst->test = f.test;
+  const int64_t slot = f.k - 1 < a.trace_cap ? f.k - 1 : (f.k - 1) % a.trace_cap;
+  double* tr = a.trace + slot * kTraceWidth;
+  tr[0] = f.pobj;
+  tr[1] = f.dobj;
+  tr[2] = f.rp;
+  tr[3] = f.rd;
+  tr[4] = f.gap;
+  tr[5] = f.test;
+  tr[6] = (double)(now - t_start) / a.wall_rate;
+  tr[7] = (double)f.k;
+  if (f.done) {
+    dst->done = 1;
+    dst->status = f.status;
+    dst->stop_iter = f.k;
+    dst->t_stop = now;
+  }
+}
+
+// Run by one wave (all lanes active) once every aux workgroup's sums are in
+// `bp`: the last aux workgroup, or a one-wave finishing launch.  Fixed-order
+// sum of the workgroups' scalar partials, then, in lane 0, the scalar steps
+// of the iteration (from the record `src`, committed to `dst`), of the
+// initialisation or of the final evaluation (into `dst`).
 template <int MODE>
-__device__ void finish_global(const SweepArgs& a, const StateIn& sv, int nb, int col_wgs) {
-  constexpr int B = 4;  // blockpart columns per lane in flight
+__device__ void finish_global(const SweepArgs& a, const StateIn& sv, int nb, int col_wgs,
+                              const DevState* src, const double* bp, DevState* dst) {
   const int lane = threadIdx.x;
+  if (is_iter(MODE)) {
+    double w[8];
+    iter_sums<true>(bp, nb, col_wgs, w);
+    if (lane != 0) return;
+    const ScalarStep f = scalar_step(sv, w, a.g.m, a.g.n, MODE == kIterB);
+    commit_step(dst, src, f, a, sv.t_start);
+    return;
+  }
+  constexpr int B = 4;  // blockpart columns per lane in flight
   double acc[kSlots];
 #pragma unroll
   for (int s = 0; s < kSlots; ++s) acc[s] = 0.0;
@@ -295,102 +426,23 @@ __device__ void finish_global(const SweepArgs& a, const StateIn& sv, int nb, int
     for (int u = 0; u < B; ++u) {
       const int k = k0 + u * kWave + lane;
 #pragma unroll
-      for (int s = 0; s < kSlots; ++s) {
-        bool use = k < nb;
-        if (is_iter(MODE)) {
-          if (s == kSR || s == kSR2 || s == kSPphi) use = use && k >= col_wgs;
-          else if (s == kSS || s == kSS2 || s == kSQpsi) use = use && k < col_wgs;
-          else if (s != kST0 && s != kST1) use = false;
-        }
-        v[u][s] = use ? load_agent(a.blockpart + (int64_t)s * nb + k) : 0.0;
-      }
+      for (int s = 0; s < kSlots; ++s)
+        v[u][s] = k < nb ? load_agent(bp + (int64_t)s * nb + k) : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < B; ++u)
 #pragma unroll
       for (int s = 0; s < kSlots; ++s) acc[s] += v[u][s];
   }
-  if (is_iter(MODE)) {
-    double w[8] = {acc[kSR], acc[kSR2], acc[kSPphi], acc[kSS],
-                   acc[kSS2], acc[kSQpsi], acc[kST0], acc[kST1]};
-    wave_sum_n(w);
-    acc[kSR] = w[0];
-    acc[kSR2] = w[1];
-    acc[kSPphi] = w[2];
-    acc[kSS] = w[3];
-    acc[kSS2] = w[4];
-    acc[kSQpsi] = w[5];
-    acc[kST0] = w[6];
-    acc[kST1] = w[7];
-  } else {
-    wave_sum_n(acc);
-  }
+  wave_sum_n(acc);
   if (lane != 0) return;
 
-  DevState* st = a.st;
+  DevState* st = dst;
   const int64_t m = a.g.m, n = a.g.n;
   const double mn = (double)(m + n);
   const double rho = sv.rho;
   const uint64_t now = wall_clock64();
-  if (is_iter(MODE)) {
-    // kIterB has no <C,X> and no dual residual (C is not read): it records
-    // NaN for them and can only stop at max_iter.
-    const double beta = acc[kSR] / mn;
-    const double alpha = sv.alpha;
-    const double cc = 2.0 * beta - alpha;
-    const double cphi = cc / (double)n, cpsi = cc / (double)m;
-    const double nan = __builtin_nan("");
-    const double pobj = MODE == kIterB ? nan : acc[kST0];
-    const double dobj = (acc[kSPphi] + cphi * sv.sum_p + acc[kSQpsi] + cpsi * sv.sum_q) / rho;
-    const double gap = fabs(pobj - dobj);
-    const double rp = sqrt(acc[kSR2] + acc[kSS2]);
-    const double rd = MODE == kIterB ? nan : sqrt(acc[kST1]) / rho;
-    const double ep = rp / fmax(sv.norm_pq, 1e-300);
-    const double ed = rd / fmax(sv.norm_c, 1e-300);
-    const double eg = gap / fmax(fmax(fabs(pobj), fabs(dobj)), 1e-300);
-    const double test = sv.tol_mode ? fmax(rp, fmax(rd, gap)) : fmax(ep, fmax(ed, eg));
-    const int64_t k = sv.iter + 1;
-    const double alpha_next = alpha - beta;
-    st->alpha = alpha_next;
-    st->cphi = cphi;
-    st->cpsi = cpsi;
-    st->iter = k;
-    st->t_last = now;
-    st->pobj = pobj;
-    st->dobj = dobj;
-    st->rp = rp;
-    st->rd = rd;
-    st->gap = gap;
-    st->test = test;
-    const int64_t slot = k - 1 < a.trace_cap ? k - 1 : (k - 1) % a.trace_cap;
-    double* tr = a.trace + slot * kTraceWidth;
-    tr[0] = pobj;
-    tr[1] = dobj;
-    tr[2] = rp;
-    tr[3] = rd;
-    tr[4] = gap;
-    tr[5] = test;
-    tr[6] = (double)(now - sv.t_start) / a.wall_rate;
-    tr[7] = (double)k;
-    int done = 0, status = 0;
-    if ((MODE != kIterB && !finite_d(test)) || !finite_d(alpha_next) || !finite_d(cc) ||
-        !finite_d(rp)) {
-      done = 1;
-      status = -3;
-    } else if (MODE != kIterB && test <= sv.tol) {
-      done = 1;
-      status = 0;
-    } else if (k >= sv.max_iter) {
-      done = 1;
-      status = 1;
-    }
-    if (done) {
-      st->done = 1;
-      st->status = status;
-      st->stop_iter = k;
-      st->t_stop = now;
-    }
-  } else if (is_final(MODE)) {
+  if (is_final(MODE)) {
     const double pobj = acc[kST0];
     const double dobj = (acc[kSPphi] + acc[kSQpsi]) / rho;
     st->f_pobj = pobj;
@@ -645,7 +697,7 @@ __device__ __forceinline__ void aux_body(const SweepArgs& a, const int b, const 
   prev = __builtin_amdgcn_readfirstlane(prev);
   if (prev != (unsigned)(nb - 1)) return;
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  finish_global<MODE>(a, sv, nb, col_wgs);
+  finish_global<MODE>(a, sv, nb, col_wgs, a.st, a.blockpart, a.st);
   if (lane == 0)
     __hip_atomic_store(&a.st->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -655,14 +707,21 @@ __global__ __launch_bounds__(kBlock) void aux_kernel(SweepArgs a) {
   aux_body<T, MODE, WIDE, SPLIT>(a, blockIdx.x, gridDim.x);
 }
 
-// The scalar steps after a split aux launch: one wave.
+// The scalar steps after a publish-only aux launch: one wave.  They read the
+// record and sums of the aux launch (a.st, a.blockpart), or in the pending
+// form (a.st_prev, a.bp_prev), and commit into a.st.
 template <int MODE>
 __device__ __forceinline__ void finish_body(const SweepArgs& a) {
-  const StateIn sv = load_state(a.st);
-  if (is_iter(MODE) && sv.done) return;
+  const DevState* src = a.st_prev ? a.st_prev : a.st;
+  const double* bp = a.st_prev ? a.bp_prev : a.blockpart;
+  const StateIn sv = load_state(src);
+  if (is_iter(MODE) && sv.done) {
+    if (src != a.st && threadIdx.x == 0) *a.st = *src;  // carry the stopped state forward
+    return;
+  }
   const int nb = (int)aux_workgroups(a.g.m, a.g.n);
   const int col_wgs = (int)((a.g.n + kAuxCols - 1) / kAuxCols);
-  finish_global<MODE>(a, sv, nb, col_wgs);
+  finish_global<MODE>(a, sv, nb, col_wgs, src, bp, a.st);
 }
 
 template <int MODE>
@@ -1059,12 +1118,52 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a, const int ct, con
   constexpr bool kReadX = MODE != kInitPQ;
   constexpr bool kWriteX = MODE != kInitX && MODE != kFinal;
 
-  DevState* st = a.st;
-  if (is_iter(MODE) && st->done) return;
+  // The state entering this iteration.  Pending form (a.st_prev set): every
+  // wave closes the previous iteration itself from its record and its aux
+  // sums (the same fixed-order arithmetic everywhere, so every workgroup
+  // takes the same shift and the same stop decision), and workgroup 0
+  // commits the result to a.st, which no other workgroup reads here.
+  const int64_t m = a.g.m, n = a.g.n;
+  const DevState* st = is_iter(MODE) && a.st_prev ? a.st_prev : a.st;
+  double shift_d = 0.0;
+  if (is_iter(MODE)) {
+    if (a.st_prev) {
+      // Wave 0 closes the previous iteration (the sums' loads issued first,
+      // the record's next) and hands the shift and the stop decision to the
+      // other waves through LDS.
+      __shared__ double closing[2];
+      if (threadIdx.x < kWave) {
+        double w[8];
+        iter_sums<false>(a.bp_prev, (int)aux_workgroups(m, n),
+                         (int)((n + kAuxCols - 1) / kAuxCols), w);
+        const StateIn pv = load_state(a.st_prev);
+        double sh = 0.0, stop = 1.0;
+        if (pv.done) {
+          if (blockIdx.x == 0 && threadIdx.x == 0) *a.st = *a.st_prev;
+        } else {
+          const ScalarStep f = scalar_step(pv, w, m, n, a.prev_b != 0);
+          if (blockIdx.x == 0 && threadIdx.x == 0) commit_step(a.st, a.st_prev, f, a, pv.t_start);
+          sh = f.cphi + f.cpsi;
+          stop = f.done ? 1.0 : 0.0;
+        }
+        if (threadIdx.x == 0) {
+          closing[0] = sh;
+          closing[1] = stop;
+        }
+      }
+      __syncthreads();
+      if (closing[1] != 0.0) return;
+      shift_d = closing[0];
+    } else {
+      if (st->done) return;
+      shift_d = st->cphi + st->cpsi;
+    }
+  } else if (is_final(MODE)) {
+    shift_d = st->cphi + st->cpsi;
+  }
 
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int64_t m = a.g.m, n = a.g.n;
   const int64_t col0 = (int64_t)ct * W;
   const int rpw = (a.g.rows + kWaves - 1) / kWaves;
 
@@ -1121,7 +1220,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a, const int ct, con
   A shift = 0, rho = 0;
   T rhoT = 0;
   if (is_iter(MODE) || is_final(MODE)) {
-    shift = (A)(st->cphi + st->cpsi);
+    shift = (A)shift_d;
     rho = (A)st->rho;
     rhoT = (T)st->rho;
   }
@@ -1524,10 +1623,12 @@ __global__ __launch_bounds__(kBlock) void maxc_kernel(SweepArgs a) {
 // (its release fence), so above kAuxSplitMin workgroups the aux kernel only
 // publishes its sums and a one-wave kernel does the scalar steps.
 template <typename T, int MODE, bool WIDE>
-hipError_t aux_go(const SweepArgs& a, hipStream_t s) {
+hipError_t aux_go(const SweepArgs& a, hipStream_t s, bool publish) {
   const int64_t nb = aux_workgroups(a.g.m, a.g.n);
   const dim3 grid((unsigned)nb);
-  if (nb >= kAuxSplitMin) {
+  if (publish) {
+    hipLaunchKernelGGL((aux_kernel<T, MODE, WIDE, true>), grid, dim3(kBlock), 0, s, a);
+  } else if (nb >= kAuxSplitMin) {
     hipLaunchKernelGGL((aux_kernel<T, MODE, WIDE, true>), grid, dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL((finish_kernel<MODE>), dim3(1), dim3(kWave), 0, s, a);
   } else {
@@ -1537,28 +1638,41 @@ hipError_t aux_go(const SweepArgs& a, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t aux_type(int mode, bool wide, const SweepArgs& a, hipStream_t s) {
+hipError_t aux_type(int mode, bool wide, const SweepArgs& a, hipStream_t s, bool publish) {
+  if (publish && !is_iter(mode)) return hipErrorInvalidValue;
   if (wide && std::is_same<T, float>::value) {
     // Float64 partials of the compensated float32 iteration.
     if (mode != kIter) return hipErrorInvalidValue;
-    return aux_go<T, kIter, true>(a, s);
+    return aux_go<T, kIter, true>(a, s, publish);
   }
   switch (mode) {
     case kIter:
-    case kIterA: return aux_go<T, kIter, false>(a, s);
-    case kIterB: return aux_go<T, kIterB, false>(a, s);
+    case kIterA: return aux_go<T, kIter, false>(a, s, publish);
+    case kIterB: return aux_go<T, kIterB, false>(a, s, publish);
     case kInitPQ:
-    case kInitX: return aux_go<T, kInitPQ, false>(a, s);
+    case kInitX: return aux_go<T, kInitPQ, false>(a, s, false);
     case kFinal:
-    case kFinalW: return aux_go<T, kFinal, false>(a, s);
+    case kFinalW: return aux_go<T, kFinal, false>(a, s, false);
   }
   return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-hipError_t launch_aux(int dtype, int mode, const SweepArgs& a, hipStream_t s, bool wide) {
-  return dtype == 0 ? aux_type<float>(mode, wide, a, s) : aux_type<double>(mode, wide, a, s);
+hipError_t launch_aux(int dtype, int mode, const SweepArgs& a, hipStream_t s, bool wide,
+                      bool publish) {
+  return dtype == 0 ? aux_type<float>(mode, wide, a, s, publish)
+                    : aux_type<double>(mode, wide, a, s, publish);
+}
+
+hipError_t launch_finish(int mode, const SweepArgs& a, hipStream_t s) {
+  if (mode == kIter || mode == kIterA)
+    hipLaunchKernelGGL((finish_kernel<kIter>), dim3(1), dim3(kWave), 0, s, a);
+  else if (mode == kIterB)
+    hipLaunchKernelGGL((finish_kernel<kIterB>), dim3(1), dim3(kWave), 0, s, a);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 hipError_t launch_sweep(int dtype, int mode, const TileCfg& t, const SweepArgs& a,

@@ -164,15 +164,18 @@ __global__ void cast_bf16(const float* __restrict__ x, bf16* __restrict__ y, int
   if (i < count) y[i] = to_bf16(x[i]);
 }
 
-// Adam on the float32 master weights; refreshes the bfloat16 copy.
+// Adam on the float32 master weights; refreshes the bfloat16 copy.  The
+// coefficients b1, 1 - b1, b2, 1 - b2 and the bias corrections c1, c2 come
+// from the host rounded once from float64 (1 - b2 formed in float32 from the
+// rounded b2 would be 1.3e-5 off).
 __global__ void adam(float* __restrict__ w, bf16* __restrict__ wb, const float* __restrict__ g,
                      float* __restrict__ m1, float* __restrict__ m2, int64_t count, float lr,
-                     float b1, float b2, float eps, float c1, float c2) {
+                     float b1, float ob1, float b2, float ob2, float eps, float c1, float c2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
   const float gi = g[i];
-  const float a = b1 * m1[i] + (1.f - b1) * gi;
-  const float b = b2 * m2[i] + (1.f - b2) * gi * gi;
+  const float a = b1 * m1[i] + ob1 * gi;
+  const float b = b2 * m2[i] + ob2 * gi * gi;
   m1[i] = a;
   m2[i] = b;
   const float v = w[i] - lr * (a / c1) / (sqrtf(b / c2) + eps);
@@ -425,10 +428,11 @@ namespace {
 // One Adam step with the gradient in `g` (device, flat parameter order).
 int adam_step(drot_mlp* n, const float* g, float lr, hipStream_t s) {
   n->step += 1;
-  const float b1 = 0.9f, b2 = 0.999f;
-  const float c1 = 1.f - std::pow(b1, (float)n->step), c2 = 1.f - std::pow(b2, (float)n->step);
+  const double b1 = 0.9, b2 = 0.999;
+  const double c1 = 1.0 - std::pow(b1, (double)n->step), c2 = 1.0 - std::pow(b2, (double)n->step);
   hipLaunchKernelGGL(adam, dim3(nblk(n->n_params)), dim3(256), 0, s, n->w, n->wb, g, n->m1,
-                     n->m2, n->n_params, lr, b1, b2, 1e-8f, c1, c2);
+                     n->m2, n->n_params, lr, (float)b1, (float)(1.0 - b1), (float)b2,
+                     (float)(1.0 - b2), 1e-8f, (float)c1, (float)c2);
   MHIP(hipGetLastError());
   return DROT_OK;
 }
