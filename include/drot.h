@@ -226,6 +226,26 @@ int drot_solve(drot_ctx *ctx, int64_t m, int64_t n, int dtype, const void *C, in
                double *mu, double *nu, const double *mu0, const double *nu0, drot_result *out,
                void *stream);
 
+/* drot_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops that must not call hipMalloc, harnesses that
+ * forbid it).  The same computation as drot_solve on the calling thread's
+ * current HIP device, with no context: the workspace (state record, partial
+ * sums, dual vectors, trace) is a static device array of 32 MiB that every
+ * GPU the library runs on holds from its first call until the process ends,
+ * and iterations are launched one by one (no graphs, no events, no streams,
+ * no pinned memory are created).  The caller passes C, p, q, X, mu, nu, mu0,
+ * nu0 and `out` as for drot_solve.  A problem whose workspace exceeds the
+ * scratch (square problems up to about 9984 x 9984 in float32 and 9472 x
+ * 9472 in float64 fit) returns DROT_EINVAL before any device work;
+ * DROT_FLAG_TIME_SWEEP returns DROT_EUNSUPPORTED.  All calls on
+ * one GPU share its scratch, whose contents persist between calls (every
+ * call initialises what it reads): calls that overlap in time on one GPU --
+ * from several host threads or streams -- race and must not be made. */
+int drot_solve_noalloc(int64_t m, int64_t n, int dtype, const void *C, int64_t ldc,
+                       const void *p, const void *q, const drot_params *params, void *X,
+                       int64_t ldx, double *mu, double *nu, const double *mu0,
+                       const double *nu0, drot_result *out, void *stream);
+
 /* ---- step-wise interface (same computation, split at its natural seams) -- */
 
 /* Bind a problem to the context and run the initialisation of Algorithm 1

@@ -12,6 +12,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -57,9 +58,11 @@ struct drot_ctx {
   hipStream_t cap_stream = nullptr;  // private stream used only for capture
   double wall_rate = 1e8;
 
-  // Workspace (one allocation, carved up per bind).
+  // Workspace (one allocation, carved up per bind).  fixed_ws: the workspace
+  // is the library's static scratch (drot_solve_noalloc), never grown.
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  bool fixed_ws = false;
   DevState* st = nullptr;        // device
   DevState* st_host = nullptr;   // pinned mirror
   double* trace = nullptr;
@@ -278,6 +281,11 @@ size_t workspace_layout(int64_t m, int64_t n, const Geometry& g, size_t* offs) {
 int ensure_workspace(drot_ctx* c, int64_t m, int64_t n, const Geometry& g, size_t* offs) {
   const size_t o = workspace_layout(m, n, g, offs);
   if (o <= c->ws_bytes) return DROT_OK;
+  if (c->fixed_ws)
+    return fail(DROT_EINVAL,
+                "a %lld x %lld problem needs %zu bytes of workspace, more than the %zu bytes of "
+                "static scratch",
+                (long long)m, (long long)n, o, c->ws_bytes);
   drop_graph(c);
   if (c->ws) {
     (void)hipDeviceSynchronize();
@@ -1110,3 +1118,82 @@ int drot_solve(drot_ctx* c, int64_t m, int64_t n, int dtype, const void* C, int6
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// drot_solve without allocation: the workspace is a static device array.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+constexpr int kMaxDevices = 64;
+
+// Device-side workspace of drot_solve_noalloc, one copy per GPU for the life
+// of the process.  In host code `scratch` names a host-side stand-in: its
+// device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_address(int device, void** ptr) {
+  if (device < 0 || device >= kMaxDevices)
+    return fail(DROT_EDEVICE, "device %d beyond the %d the static scratch supports", device,
+                kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(DROT_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[device] = p;
+  }
+  *ptr = g_scratch_ptr[device];
+  return DROT_OK;
+}
+
+}  // namespace
+
+extern "C" int drot_solve_noalloc(int64_t m, int64_t n, int dtype, const void* C, int64_t ldc,
+                                  const void* p, const void* q, const drot_params* params,
+                                  void* X, int64_t ldx, double* mu, double* nu, const double* mu0,
+                                  const double* nu0, drot_result* out, void* stream) {
+  if (!out) return fail(DROT_EINVAL, "out is NULL");
+  drot_cost cost{};
+  cost.kind = DROT_COST_DENSE;
+  cost.data = C;
+  cost.ld = ldc;
+  int rc = validate(m, n, dtype, &cost, p, q, params, X, ldx, mu0, nu0);
+  if (rc) return rc;
+  if (params->flags & DROT_FLAG_TIME_SWEEP)
+    return fail(DROT_EUNSUPPORTED, "sweep timing needs events, which drot_solve_noalloc does not "
+                                   "create");
+  // Size check before any device call.
+  Geometry g;
+  if ((rc = choose_geometry(dtype, m, n, &cost, X, ldx, params, &g))) return rc;
+  size_t offs[12];
+  const size_t need = workspace_layout(m, n, g, offs);
+  if (need > kScratchBytes)
+    return fail(DROT_EINVAL,
+                "a %lld x %lld problem needs %zu bytes of workspace, more than the %zu bytes of "
+                "static scratch of drot_solve_noalloc",
+                (long long)m, (long long)n, need, kScratchBytes);
+  int device = 0;
+  HIP_TRY(hipGetDevice(&device));
+  void* ptr = nullptr;
+  if ((rc = scratch_address(device, &ptr))) return rc;
+
+  drot_ctx c;  // on the stack: no stream, no pinned memory, no graphs, no events
+  c.device = device;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
+    c.wall_rate = (double)khz * 1000.0;
+  DevState host_state{};
+  c.st_host = &host_state;
+  c.ws = ptr;
+  c.ws_bytes = kScratchBytes;
+  c.fixed_ws = true;
+  drot_params prm = *params;
+  prm.flags |= DROT_FLAG_NO_GRAPH;  // launches only: instantiating a graph allocates
+  return drot_solve_cost(&c, m, n, dtype, &cost, p, q, &prm, X, ldx, mu, nu, mu0, nu0, out,
+                         stream);
+}

@@ -33,7 +33,7 @@ EXPORTED = ("drot_version", "drot_strerror", "drot_last_error", "drot_ctx_create
             "drot_solve_batched", "drot_mlp_create", "drot_mlp_destroy", "drot_mlp_num_params",
             "drot_mlp_set_weights", "drot_mlp_get_weights", "drot_mlp_forward",
             "drot_mlp_gradients", "drot_mlp_train_step", "drot_mlp_apply_gradients", "drot_tune",
-            "drot_checkpoint_size", "drot_checkpoint", "drot_resume")
+            "drot_checkpoint_size", "drot_checkpoint", "drot_resume", "drot_solve_noalloc")
 
 
 class Params(ctypes.Structure):
@@ -101,6 +101,7 @@ def lib():
     L.drot_ctx_destroy.argtypes = [vp]
     common = [vp, i64, i64, i32, vp, i64, vp, vp, ctypes.POINTER(Params), vp, i64]
     L.drot_solve.argtypes = common + [vp, vp, vp, vp, ctypes.POINTER(Result), vp]
+    L.drot_solve_noalloc.argtypes = common[1:] + [vp, vp, vp, vp, ctypes.POINTER(Result), vp]
     L.drot_bind.argtypes = common + [vp, vp, vp]
     L.drot_iterate.argtypes = [vp, i64, vp]
     L.drot_poll.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int32), vp]
@@ -474,3 +475,16 @@ def solve(C, p, q, rho: float, tol: float = 1e-4, max_iter: int = 100000,
                       tile_groups)
     X, res = ctx.solve(C, p, q, prm, X=X, mu=mu, nu=nu, mu0=mu0, nu0=nu0, stream=stream)
     return X, res, mu, nu
+
+
+def solve_noalloc(C, p, q, params: Params, X, mu=None, nu=None, mu0=None, nu0=None,
+                  stream=None):
+    """drot_solve_noalloc: the caller provides X (and optionally mu, nu); the
+    library allocates nothing.  Returns (status, result dict)."""
+    m, n = C.shape
+    r = Result()
+    rc = lib().drot_solve_noalloc(m, n, _dtype_code(C), _ptr(C), _ld(C), _ptr(p), _ptr(q),
+                                  ctypes.byref(params), _ptr(X), _ld(X), _ptr(mu), _ptr(nu),
+                                  _ptr(mu0), _ptr(nu0), ctypes.byref(r), _stream(stream))
+    _check(rc)
+    return rc, r.as_dict()

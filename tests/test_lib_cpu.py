@@ -134,3 +134,21 @@ def test_cost_descriptor_validation_without_device(lib):
     # a valid descriptor reaches the context check
     assert go(drot.Cost(drot.COST_COORDS, 3, None, 0, 4096, 8192, 0.0)) == drot.EINVAL
     assert "ctx" in drot.last_error()
+
+
+def test_noalloc_refuses_oversized_problem_before_device_work():
+    """drot_solve_noalloc checks the workspace of the problem against its
+    static scratch before any HIP call (here without a GPU): a 20000 x 20000
+    problem is refused with DROT_EINVAL."""
+    import ctypes
+    from paper_2110_11738_amd import drot
+    L = drot.lib()
+    r = drot.Result()
+    prm = drot.make_params(1e-5, 0.0, 10)
+    vp = ctypes.c_void_p
+    big = 20000
+    rc = L.drot_solve_noalloc(big, big, drot.F32, vp(1 << 12), big, vp(1 << 44), vp(1 << 44),
+                              ctypes.byref(prm), vp(1 << 40), big, None, None, None, None,
+                              ctypes.byref(r), None)
+    assert rc == drot.EINVAL
+    assert "static scratch" in drot.last_error()
