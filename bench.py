@@ -224,9 +224,11 @@ def precision_section(ctx, steps=200, warmup=20):
     return out
 
 
-def batch_section(ctx, count=512, iters=100):
-    """512 ragged problems (m, n uniform in [64, 2048]) advanced together for
-    a fixed number of iterations, against the same problems solved one by one."""
+def batch_section(ctx, count=512, iters=100, tol_rho0=2.0, tol=1e-4, n_seq=64):
+    """512 ragged problems (m, n uniform in [64, 2048]): the tuner's schedules
+    per size class (drot_tune_batched), a fixed number of iterations batched
+    against the same problems one by one, and every problem solved to the
+    1e-4 relative test batched against the first n_seq of them one by one."""
     import numpy as np
     import torch
     from gen import config_batch
@@ -240,17 +242,39 @@ def batch_section(ctx, count=512, iters=100):
         probs.append({"C": drot.padded(torch.from_numpy(I.C.astype(np.float32)).cuda()),
                       "p": torch.from_numpy(I.p.astype(np.float32)).cuda(),
                       "q": torch.from_numpy(I.q.astype(np.float32)).cuda(),
-                      "rho": I.rho, "tol": 0.0})
+                      "rho": I.rho, "tol": 0.0, "m": I.m, "n": I.n})
         entries += I.m * I.n
     del insts
     drot.solve_batched(probs[:8], max_iter=5, ctx=ctx)  # warm-up
     torch.cuda.synchronize()
+    # untuned (default schedule: items of about 65 536 entries)
+    t0 = time.perf_counter()
+    rc, outs = drot.solve_batched(probs, max_iter=iters, check_every=50, ctx=ctx)
+    torch.cuda.synchronize()
+    t_untuned = time.perf_counter() - t0
+    del outs
+    t0 = time.perf_counter()
+    table = drot.tune_batched(probs, iters=64, check_every=32, ctx=ctx)
+    torch.cuda.synchronize()
+    t_tune = time.perf_counter() - t0
+    log(f"batch tuner: {len(table)} size classes in {t_tune:.1f}s")
     t0 = time.perf_counter()
     rc, outs = drot.solve_batched(probs, max_iter=iters, check_every=50, ctx=ctx)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     assert all(o[1]["iters"] == iters for o in outs)
     del outs
+    # steady state: the difference of two runs (setup, initialisation and the
+    # final pass cancel)
+    t0 = time.perf_counter()
+    rc, outs = drot.solve_batched(probs, max_iter=3 * iters, check_every=50, ctx=ctx)
+    torch.cuda.synchronize()
+    t_batch3 = time.perf_counter() - t0
+    del outs
+    per_iter = (t_batch3 - t_batch) / (2 * iters)
+    gbs_ss = 12.0 * entries / per_iter / 1e9
+    log(f"batched steady state: {per_iter * 1e3:.3f} ms per iteration, {gbs_ss:.0f} GB/s "
+        f"({100 * gbs_ss / HBM_PEAK_GBS:.1f}% of peak)")
     t0 = time.perf_counter()
     for pr in probs:
         drot.solve(pr["C"], pr["p"], pr["q"], pr["rho"], tol=0.0, max_iter=iters, check_every=50,
@@ -258,12 +282,49 @@ def batch_section(ctx, count=512, iters=100):
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
     gbs = 12.0 * entries * iters / t_batch / 1e9
-    log(f"batch of {count}: {t_batch:.3f}s batched vs {t_seq:.3f}s one by one "
-        f"({t_seq / t_batch:.1f}x), {gbs:.0f} GB/s")
-    return {"problems": count, "iterations": iters, "entries": entries,
-            "seconds_batched": t_batch, "seconds_one_by_one": t_seq,
-            "speedup": t_seq / t_batch, "achieved_GBs": gbs,
-            "workload": "config_batch: m, n ~ U[64, 2048], 2-D blob clouds, Dirichlet(1), float32"}
+    log(f"batch of {count} x {iters} iterations: {t_batch:.3f}s batched (tuned; untuned "
+        f"{t_untuned:.3f}s) vs {t_seq:.3f}s one by one ({t_seq / t_batch:.1f}x), {gbs:.0f} GB/s "
+        f"({100 * gbs / HBM_PEAK_GBS:.1f}% of peak)")
+    out = {"problems": count, "iterations": iters, "entries": entries,
+           "seconds_batched": t_batch, "seconds_batched_untuned": t_untuned,
+           "seconds_one_by_one": t_seq, "speedup": t_seq / t_batch, "achieved_GBs": gbs,
+           "frac": gbs / HBM_PEAK_GBS, "steady_ms_per_iter": per_iter * 1e3,
+           "steady_GBs": gbs_ss, "steady_frac": gbs_ss / HBM_PEAK_GBS,
+           "tuner_seconds": t_tune, "tuned_classes": table,
+           "workload": "config_batch: m, n ~ U[64, 2048], 2-D blob clouds, Dirichlet(1), float32"}
+    # every problem to the relative test
+    for pr in probs:
+        pr["rho"] = tol_rho0 / (pr["m"] + pr["n"])
+        pr["tol"] = tol
+    t0 = time.perf_counter()
+    rc, outs = drot.solve_batched(probs, max_iter=3_000_000, check_every=64, ctx=ctx)
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t0
+    its = [o[1]["iters"] for o in outs]
+    n_conv = sum(1 for o in outs if o[1]["status"] == 0)
+    del outs
+    log(f"batched {count} to {tol:g} (rho0 = {tol_rho0:g}): {t_all:.2f}s, {n_conv} converged, "
+        f"iterations {min(its)}..{max(its)}")
+    t0 = time.perf_counter()
+    rc, outs = drot.solve_batched(probs[:n_seq], max_iter=3_000_000, check_every=64, ctx=ctx)
+    torch.cuda.synchronize()
+    t_sub_b = time.perf_counter() - t0
+    del outs
+    t0 = time.perf_counter()
+    for k, pr in enumerate(probs[:n_seq]):
+        drot.solve(pr["C"], pr["p"], pr["q"], pr["rho"], tol=tol, max_iter=3_000_000,
+                   check_every=64, ctx=ctx)
+        if k % 16 == 15:
+            log(f"  one by one: {k + 1}/{n_seq}, {time.perf_counter() - t0:.0f}s")
+    torch.cuda.synchronize()
+    t_sub_s = time.perf_counter() - t0
+    log(f"first {n_seq} to {tol:g}: batched {t_sub_b:.2f}s vs one by one {t_sub_s:.2f}s")
+    out["time_to_tol"] = {"tol": tol, "rho0": tol_rho0, "seconds_batched_all": t_all,
+                          "converged": n_conv, "iters_min": min(its), "iters_max": max(its),
+                          "iters_mean": float(np.mean(its)), "subset": n_seq,
+                          "seconds_batched_subset": t_sub_b, "seconds_one_by_one_subset": t_sub_s,
+                          "ratio_subset": t_sub_b / t_sub_s}
+    return out
 
 
 def protocol_runs(ctx, bind, runs=10, iters=100):
@@ -642,6 +703,8 @@ def main():
                     help="the paper's runtime protocol at m = n from 100 to 20000")
     ap.add_argument("--large-only", action="store_true",
                     help="skip every section before the large instance (profiling runs)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the batched-solver section (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration for profiles)")
     ap.add_argument("--check-every", type=int, default=64)
@@ -661,6 +724,12 @@ def main():
     drot.lib()
     ctx = drot.Context(0)
 
+    if args.batch_only:
+        out = {"metric": "batched DROT (profiling run)", "batch_only": True,
+               "batch": batch_section(ctx)}
+        ctx.close()
+        print(json.dumps(out), flush=True)
+        return
     if args.large_only:
         out = {"metric": "DROT iters/s at 20000^2 (profiling run)", "large_only": True}
         C = p = q = None

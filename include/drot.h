@@ -319,19 +319,54 @@ typedef struct {
 } drot_problem;
 
 /* Solve `count` independent problems of any shapes together: every iteration
- * is one batched sweep launch, one batched aux launch over the (problem, tile)
- * work items of the problems still running and one finishing launch (one
+ * is one batched sweep launch, one batched aux launch over the (problem, work
+ * item) pairs of the problems still running and one finishing launch (one
  * wave per problem), replayed as hipGraphs of
  * params->check_every iterations.  Each problem runs Algorithm 1 with its own
  * stopping test and stops on its own; finished problems leave the work lists
  * when they make up half of them.  params supplies max_iter, tol_mode,
- * check_every, cache_mode, tile_rows, tile_chunks and DROT_FLAG_NO_GRAPH; one
- * tile variant serves the whole batch.  outs[count] receives one result per
+ * check_every, cache_mode, tile_rows, tile_chunks, tile_groups and
+ * DROT_FLAG_NO_GRAPH; each problem's sweep schedule (rows per block, blocks
+ * per work item) comes from the context's tuner cache for its size class
+ * (drot_tune_batched) unless tile_rows / tile_groups set it.  outs[count] receives one result per
  * problem.  Returns DROT_OK when every problem met its test, DROT_MAXITER if
  * some hit max_iter, or an error (the message names the problem).  The call
  * uses the context's workspace and releases a problem bound by drot_bind. */
 int drot_solve_batched(drot_ctx *ctx, int32_t count, int dtype, const drot_problem *probs,
                        const drot_params *params, drot_result *outs, void *stream);
+
+/* Autotuner of the batched sweep's schedule.  Not an operation of the paper:
+ * a batch mixes problems of very different shapes, and the shape of a sweep
+ * work item -- 16-byte chunks per lane (the strip width), rows per block and
+ * row blocks per item -- decides how long each workgroup lives and how many
+ * column partials the aux kernel adds.  Problems are grouped by size class
+ * of (m, n), each side in one of [1,128), [128,256), [256,512), [512,1024),
+ * [1024,2048), [2048,inf).  Stage 1 times the whole batch under one schedule
+ * for every class: chunks in {1, 2} x rows in {8, 16, 32} x blocks per item
+ * in {1, 2}.  Stage 2 revisits each class holding at least 5% of the
+ * entries, largest first, with rows in {8, 16, 32} x blocks in {1, 2, 4}
+ * while the other classes keep theirs, and keeps a change that is 1%
+ * faster.  Each timing is `iters` iterations of the whole batch (0 = two
+ * graphs of params->check_every; rounded up to whole graphs) after one warm
+ * graph, under the batch's cache policy.  The choices go to the context's
+ * tuner cache, which drot_solve_batched consults (untuned: 2 chunks, 16-row
+ * blocks, one per item; params->tile_chunks, tile_rows and tile_groups, when
+ * set, override).  `table` (host, table_cap entries, may be NULL if
+ * table_cap is 0) receives one entry per class present and *n_entries their
+ * number.  The problems' X arrays are overwritten by the trials.  Blocks
+ * until done. */
+typedef struct {
+  int32_t m_class, n_class;   /* size classes 0..5 of m and n (see above) */
+  int32_t tile_rows;          /* chosen rows per block */
+  int32_t blocks_per_item;    /* chosen row blocks per sweep work item */
+  int32_t problems;           /* problems of the class in the batch */
+  int32_t chunks;             /* chosen 16-byte chunks per lane (whole batch) */
+  double us_per_iter;         /* the whole batch per iteration with the final choices */
+} drot_batch_tile;
+
+int drot_tune_batched(drot_ctx *ctx, int32_t count, int dtype, const drot_problem *probs,
+                      const drot_params *params, int64_t iters, drot_batch_tile *table,
+                      int32_t table_cap, int32_t *n_entries, void *stream);
 
 /* ---- learned warm start: a small MLP trained with this library's kernels ---
  * Not part of the paper: a network maps (p, q) to initial dual variables

@@ -101,6 +101,13 @@ struct drot_ctx {
   int g_iters = 0;
   bool g_timed = false;
 
+  // Tuner cache of the batched solver: rows per block and row blocks per
+  // work item by size-class key (drot_batch.hip), 0 = untuned.
+  static constexpr int kBatchKeys = 2 * 2 * 36;
+  int batch_rows[kBatchKeys] = {};
+  int batch_per[kBatchKeys] = {};
+  int batch_chunks[4] = {};  // by element type and cache policy
+
   // Sweep timing (DROT_FLAG_TIME_SWEEP).
   std::vector<hipEvent_t> ev;
   double sweep_ms = 0.0;
@@ -510,6 +517,27 @@ int check_ctx(drot_ctx* c) {
 int drot_internal_fail(int code, const char* msg) { return fail(code, "%s", msg); }
 
 double drot_internal_wall_rate(const drot_ctx* c) { return c->wall_rate; }
+
+bool drot_internal_batch_tile(const drot_ctx* c, int key, int* rows, int* per_item) {
+  if (key < 0 || key >= drot_ctx::kBatchKeys || c->batch_rows[key] <= 0) return false;
+  *rows = c->batch_rows[key];
+  *per_item = c->batch_per[key];
+  return true;
+}
+
+void drot_internal_set_batch_tile(drot_ctx* c, int key, int rows, int per_item) {
+  if (key < 0 || key >= drot_ctx::kBatchKeys) return;
+  c->batch_rows[key] = rows;
+  c->batch_per[key] = per_item;
+}
+
+int drot_internal_batch_chunks(const drot_ctx* c, int key) {
+  return key >= 0 && key < 4 ? c->batch_chunks[key] : 0;
+}
+
+void drot_internal_set_batch_chunks(drot_ctx* c, int key, int chunks) {
+  if (key >= 0 && key < 4) c->batch_chunks[key] = chunks;
+}
 
 // Make the context's workspace at least `bytes` large for a batched solve.
 // The single-problem binding lives in the same workspace and is released.

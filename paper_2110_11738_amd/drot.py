@@ -33,7 +33,8 @@ EXPORTED = ("drot_version", "drot_strerror", "drot_last_error", "drot_ctx_create
             "drot_solve_batched", "drot_mlp_create", "drot_mlp_destroy", "drot_mlp_num_params",
             "drot_mlp_set_weights", "drot_mlp_get_weights", "drot_mlp_forward",
             "drot_mlp_gradients", "drot_mlp_train_step", "drot_mlp_apply_gradients", "drot_tune",
-            "drot_checkpoint_size", "drot_checkpoint", "drot_resume", "drot_solve_noalloc")
+            "drot_checkpoint_size", "drot_checkpoint", "drot_resume", "drot_solve_noalloc",
+            "drot_tune_batched")
 
 
 class Params(ctypes.Structure):
@@ -72,6 +73,13 @@ class Problem(ctypes.Structure):
                 ("X", ctypes.c_void_p), ("ldx", ctypes.c_int64), ("rho", ctypes.c_double),
                 ("tol", ctypes.c_double), ("mu", ctypes.c_void_p), ("nu", ctypes.c_void_p),
                 ("mu0", ctypes.c_void_p), ("nu0", ctypes.c_void_p)]
+
+
+class BatchTile(ctypes.Structure):
+    _fields_ = [("m_class", ctypes.c_int32), ("n_class", ctypes.c_int32),
+                ("tile_rows", ctypes.c_int32), ("blocks_per_item", ctypes.c_int32),
+                ("problems", ctypes.c_int32), ("chunks", ctypes.c_int32),
+                ("us_per_iter", ctypes.c_double)]
 
 
 class DrotError(RuntimeError):
@@ -113,6 +121,9 @@ def lib():
     L.drot_solve_cost.argtypes = cost_common + [vp, vp, vp, vp, ctypes.POINTER(Result), vp]
     L.drot_solve_batched.argtypes = [vp, ctypes.c_int32, i32, ctypes.POINTER(Problem),
                                      ctypes.POINTER(Params), ctypes.POINTER(Result), vp]
+    L.drot_tune_batched.argtypes = [vp, ctypes.c_int32, i32, ctypes.POINTER(Problem),
+                                    ctypes.POINTER(Params), i64, ctypes.POINTER(BatchTile),
+                                    ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), vp]
     fp = ctypes.POINTER(ctypes.c_float)
     dp = ctypes.POINTER(ctypes.c_double)
     L.drot_mlp_create.argtypes = [ctypes.POINTER(vp), i32, i32, i32, i32, i32, ctypes.c_uint64]
@@ -338,18 +349,11 @@ def padded(t, mult: int = 4):
     return buf[:, :n]
 
 
-def solve_batched(problems, max_iter: int = 100000, tol_mode: int = TOL_RELATIVE,
-                  check_every: int = 0, flags: int = 0, tile_rows: int = 0, tile_chunks: int = 0,
-                  cache_mode: int = CACHE_AUTO, ctx: Context | None = None, stream=None):
-    """Solve a list of problems together.  Each item is a dict with C (m x n
-    tensor), p, q, rho, tol and optionally mu0, nu0 (float64 warm start); X,
-    mu and nu are allocated here (X with a 16-byte-aligned leading dimension).
-    Returns (status, [(X, result, mu, nu), ...])."""
+def _batch_arrays(problems):
     import torch
     if not problems:
         raise ValueError("no problems")
     C0 = problems[0]["C"]
-    ctx = ctx or default_context(C0.device.index or 0)
     arr = (Problem * len(problems))()
     outs = (Result * len(problems))()
     keep = []
@@ -368,12 +372,44 @@ def solve_batched(problems, max_iter: int = 100000, tol_mode: int = TOL_RELATIVE
                          None if mu0 is None else mu0.data_ptr(),
                          None if nu0 is None else nu0.data_ptr())
         keep.append((X, mu, nu))
+    return C0, arr, outs, keep
+
+
+def solve_batched(problems, max_iter: int = 100000, tol_mode: int = TOL_RELATIVE,
+                  check_every: int = 0, flags: int = 0, tile_rows: int = 0, tile_chunks: int = 0,
+                  cache_mode: int = CACHE_AUTO, tile_groups: int = 0, ctx: Context | None = None,
+                  stream=None):
+    """Solve a list of problems together.  Each item is a dict with C (m x n
+    tensor), p, q, rho, tol and optionally mu0, nu0 (float64 warm start); X,
+    mu and nu are allocated here (X with a 16-byte-aligned leading dimension).
+    Returns (status, [(X, result, mu, nu), ...])."""
+    C0, arr, outs, keep = _batch_arrays(problems)
+    ctx = ctx or default_context(C0.device.index or 0)
     prm = make_params(1.0, 0.0, max_iter, tol_mode, X0_PQ, check_every, flags, tile_rows,
-                      tile_chunks, 0, cache_mode)
+                      tile_chunks, 0, cache_mode, tile_groups)
     rc = lib().drot_solve_batched(ctx.handle, len(problems), _dtype_code(C0), arr,
                                   ctypes.byref(prm), outs, _stream(stream))
     _check(rc)
     return rc, [(X, outs[k].as_dict(), mu, nu) for k, (X, mu, nu) in enumerate(keep)]
+
+
+def tune_batched(problems, iters: int = 0, check_every: int = 0, cache_mode: int = CACHE_AUTO,
+                 tile_chunks: int = 0, ctx: Context | None = None, stream=None):
+    """drot_tune_batched: time the candidate sweep schedules per size class
+    of the given problems (their X is overwritten) and keep the fastest in
+    the context's tuner cache.  Returns a list of dicts, one per class."""
+    C0, arr, outs, keep = _batch_arrays(problems)
+    ctx = ctx or default_context(C0.device.index or 0)
+    prm = make_params(1.0, 0.0, 10, TOL_RELATIVE, X0_PQ, check_every, 0, 0, tile_chunks, 0,
+                      cache_mode)
+    table = (BatchTile * 72)()
+    n = ctypes.c_int32()
+    rc = lib().drot_tune_batched(ctx.handle, len(problems), _dtype_code(C0), arr,
+                                 ctypes.byref(prm), int(iters), table, 72, ctypes.byref(n),
+                                 _stream(stream))
+    _check(rc, allow=(OK,))
+    return [{f: getattr(table[k], f) for f, _ in BatchTile._fields_}
+            for k in range(min(n.value, 72))]
 
 
 class MLP:

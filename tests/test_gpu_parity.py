@@ -729,3 +729,29 @@ def test_batched_per_problem_stop(ctx):
         assert abs(res["objective"] - rs["objective"]) <= 1e-4 * rs["objective"]
         iters.add(res["iters"])
     assert len(iters) > 1
+
+
+def test_batched_tuner_schedules_follow_oracle(ctx):
+    """drot_tune_batched picks a schedule (rows per block, blocks per item) per
+    size class; the tuned batched solve still follows each problem's oracle
+    trajectory, as does an explicit schedule of many blocks per item."""
+    from gen import config_batch
+    from paper_2110_11738_amd import drot
+    insts = [round_to(I, np.float32) for I in config_batch(20, 64, 700, seed=5)]
+    table = drot.tune_batched(_batch_inputs(insts, tol=0.0), iters=16, check_every=8, ctx=ctx)
+    print(f"[batch tune] {table}", flush=True)
+    assert 1 <= len(table) <= 36
+    assert sum(t["problems"] for t in table) == len(insts)
+    for t in table:
+        assert t["tile_rows"] in (8, 16, 32) and t["blocks_per_item"] in (1, 2, 4)
+        assert t["chunks"] in (1, 2) and t["us_per_iter"] > 0
+        assert 0 <= t["m_class"] <= 5 and 0 <= t["n_class"] <= 5
+    K = 25
+    for kw in ({}, {"tile_rows": 8, "tile_groups": 3}):
+        rc, outs = drot.solve_batched(_batch_inputs(insts, tol=0.0), max_iter=K, check_every=8,
+                                      ctx=ctx, **kw)
+        for I, (X, res, mu, nu) in zip(insts, outs):
+            R = ref.solve(I.C, I.p, I.q, I.rho, 0.0, max_iter=K)
+            assert res["iters"] == K
+            assert _rel_max(X.double().cpu().numpy(), R.X) <= TOL["float32"][0]
+            assert _rel_max(mu.cpu().numpy(), R.mu) <= TOL["float32"][1]
