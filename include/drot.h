@@ -106,21 +106,26 @@ typedef enum { DROT_CACHE_AUTO = 0, DROT_CACHE_CACHED = 1, DROT_CACHE_STREAM = 2
  * float32 pairs for its row, column, <C,X> and dual-residual sums, and every
  * later combination (lanes, waves, tiles, the aux kernel) is in float64, so
  * each residual carries about one float32 rounding of its terms instead of
- * one per addition.  X stays float32.  Float64 problems, and problems on
- * the one-workgroup path (drot_params), whose sums are all float64, ignore
- * the flag;
- * combined with DROT_FLAG_SKIP_C it gives DROT_EUNSUPPORTED; ragged widths
- * (n not a multiple of 4) use the 4-byte path. */
+ * one per addition.  X stays float32.  Float64 problems ignore the flag; a
+ * small float32 problem that sets it runs on sweep + aux launches (not on the
+ * one-workgroup path, whose lane partials are plain float32 sums); combined
+ * with DROT_FLAG_SKIP_C it gives DROT_EUNSUPPORTED; ragged widths (n not a
+ * multiple of 4) use the 4-byte path. */
 #define DROT_FLAG_COMPENSATED 0x8
 
-/* Small problems take a one-workgroup path: a dense cost with m <= 1024,
- * n <= 512 and m n <= 65536, all sweep-schedule fields 0, cache_mode AUTO
- * and neither DROT_FLAG_SKIP_C nor DROT_FLAG_TIME_SWEEP.  There a single
- * workgroup of 1024 threads runs many whole iterations per launch (the same
- * steps, state and stopping test, with every sum in float64), since at these
- * sizes two launches per iteration would cost more than the memory traffic;
+/* Small problems take a one-workgroup path: a dense cost whose plan fits the
+ * registers of one 1024-thread workgroup -- in float32 n <= 64 and m <= 512,
+ * n <= 128 and m <= 256, n <= 256 and m <= 128, or n <= 512 and m <= 64; in
+ * float64 half those rows -- with all sweep-schedule fields 0, cache_mode
+ * AUTO, neither DROT_FLAG_SKIP_C nor DROT_FLAG_TIME_SWEEP, and in float32 not
+ * DROT_FLAG_COMPENSATED.  There a single workgroup runs many whole
+ * iterations per launch (the same steps, state and stopping test; each
+ * lane's partial sums of at most 32 entries are in the problem's type, as in
+ * the sweep, and everything after them in float64), since at these sizes two
+ * launches per iteration would cost more than the memory traffic;
  * DROT_FLAG_NO_GRAPH has no effect on it.  Setting any tile field keeps a
- * small problem on the sweep + aux path. */
+ * small problem on the sweep + aux path.  drot_result.path reports which
+ * path ran. */
 typedef struct {
   double rho;          /* penalty parameter rho > 0 (the paper uses rho0/(m+n)) */
   double tol;          /* stopping tolerance >= 0; 0 runs exactly max_iter iterations */

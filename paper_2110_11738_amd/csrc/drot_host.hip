@@ -653,8 +653,11 @@ int drot_bind_cost(drot_ctx* c, int64_t m, int64_t n, int dtype, const drot_cost
   c->args.nu0 = nu0;
   c->geo = g;
   c->skipc = (prm->flags & DROT_FLAG_SKIP_C) != 0;
+  // A float32 problem that asks for compensated sums stays on sweep + aux:
+  // the one-workgroup path's lane partials are plain sums in the problem type.
   c->small = cost->kind == DROT_COST_DENSE &&
              !(prm->flags & (DROT_FLAG_SKIP_C | DROT_FLAG_TIME_SWEEP)) &&
+             !(dtype == DROT_F32 && (prm->flags & DROT_FLAG_COMPENSATED)) &&
              prm->tile_rows == 0 && prm->tile_chunks == 0 && prm->tile_unroll == 0 &&
              prm->tile_groups == 0 && prm->cache_mode == DROT_CACHE_AUTO &&
              small_fits(dtype, m, n);
