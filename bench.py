@@ -173,9 +173,9 @@ def tuned_tile(ctx, bind, iters=64):
 
 
 def cost_binder(ctx, m, n, cost, p, q, rho, keep):
-    import torch
     from paper_2110_11738_amd import drot
-    X = torch.empty((m, n), dtype=torch.float32, device="cuda")
+    import torch
+    X = drot.empty_plan(m, n, torch.float32, "cuda")
 
     def bind(flags, max_iter):
         prm = drot.make_params(rho, 0.0, max_iter, check_every=64, flags=flags)
@@ -195,8 +195,9 @@ def precision_section(ctx, steps=200, warmup=20):
     inst = config_cube_3d(0)
     m, n = inst.m, inst.n
     log(f"generated {inst.name} in {time.time() - t0:.1f}s")
-    C32 = torch.from_numpy(inst.C.astype(np.float32)).cuda()
-    Cb = C32.to(torch.bfloat16)
+    # rows of C and X start on 128-byte cache lines (leading dimension 15008)
+    C32 = drot.padded(torch.from_numpy(inst.C.astype(np.float32)).cuda())
+    Cb = drot.padded(C32.to(torch.bfloat16))
     xs = torch.from_numpy(inst.xs.astype(np.float32)).cuda()
     xt = torch.from_numpy(inst.xt.astype(np.float32)).cuda()
     p = torch.from_numpy(inst.p.astype(np.float32)).cuda()
@@ -204,7 +205,8 @@ def precision_section(ctx, steps=200, warmup=20):
     rho = inst.rho
     scale = float(inst.cscale)
     del inst
-    out = {"m": m, "n": n, "workload": "cube3d 10000x15000 float32 X"}
+    out = {"m": m, "n": n, "workload": "cube3d 10000x15000 float32 X",
+           "leading_dimension": C32.stride(0)}
     for name, kind, keep, bpe, fl in (
             ("dense_f32", drot.COST_DENSE, (C32,), 12, 0),
             ("dense_f32_compensated", drot.COST_DENSE, (C32,), 12, drot.FLAG_COMPENSATED),
@@ -553,15 +555,15 @@ def tol_forms_section(ctx, rho0=2.0, tol=1e-4, n_seq=64):
     inst = config_cube_3d(0)
     m, n = inst.m, inst.n
     rho = rho0 / (m + n)
-    C32 = torch.from_numpy(inst.C.astype(np.float32)).cuda()
-    Cb = C32.to(torch.bfloat16)
+    C32 = drot.padded(torch.from_numpy(inst.C.astype(np.float32)).cuda())
+    Cb = drot.padded(C32.to(torch.bfloat16))
     xs = torch.from_numpy(inst.xs.astype(np.float32)).cuda()
     xt = torch.from_numpy(inst.xt.astype(np.float32)).cuda()
     p = torch.from_numpy(inst.p.astype(np.float32)).cuda()
     q = torch.from_numpy(inst.q.astype(np.float32)).cuda()
     scale = float(inst.cscale)
     del inst
-    X = torch.empty((m, n), dtype=torch.float32, device="cuda")
+    X = drot.empty_plan(m, n, torch.float32, "cuda")
     forms = {}
     for name, kind, keep, fl in (("dense_f32", drot.COST_DENSE, (C32,), 0),
                                  ("dense_f32_compensated", drot.COST_DENSE, (C32,),
@@ -671,6 +673,18 @@ def _cpu_model():
     return "unknown"
 
 
+def calibrate_copy(torch, out):
+    """A plain copy of known size: under `rocprofv3 --pmc FETCH_SIZE` (or
+    WRITE_SIZE) its counters give the factor that converts the sweep's
+    counters into bytes."""
+    src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    out["copy_calibration_bytes"] = src.numel() * 4
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -705,6 +719,8 @@ def main():
                     help="skip every section before the large instance (profiling runs)")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the batched-solver section (profiling runs)")
+    ap.add_argument("--precision-only", action="store_true",
+                    help="only the 10000 x 15000 precision section (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration for profiles)")
     ap.add_argument("--check-every", type=int, default=64)
@@ -724,6 +740,14 @@ def main():
     drot.lib()
     ctx = drot.Context(0)
 
+    if args.precision_only:
+        out = {"metric": "DROT precision forms at 10000x15000 (profiling run)",
+               "precision_only": True, "precision": precision_section(ctx)}
+        if args.calibrate_copy:
+            calibrate_copy(torch, out)
+        ctx.close()
+        print(json.dumps(out), flush=True)
+        return
     if args.batch_only:
         out = {"metric": "batched DROT (profiling run)", "batch_only": True,
                "batch": batch_section(ctx)}
@@ -897,15 +921,7 @@ def main():
         out["time_to_tol_forms"] = tol_forms_section(ctx, rho0=args.tol_forms_rho0)
 
     if args.calibrate_copy:
-        # A plain copy of known size: under `rocprofv3 --pmc FETCH_SIZE` (or
-        # WRITE_SIZE) its counters give the factor that converts the sweep's
-        # counters into bytes.
-        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(5):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        out["copy_calibration_bytes"] = src.numel() * 4
+        calibrate_copy(torch, out)
 
     ctx.close()
     print(json.dumps(out), flush=True)
