@@ -8,11 +8,12 @@ m x n plan plus the O(m+n) dual update and the stopping test.  The timed
 workload is the 4096 x 4096 float32 problem (2-D five-Gaussian point clouds,
 squared-Euclidean cost normalised to max 1, Dirichlet(1) marginals,
 rho = (1/ln m)/(m+n)), resident in HBM before timing starts.  One JSON line
-is printed with iterations/s (`value`, graph replays without events), the
-roofline of the sweep kernel (a second timed region of the same length with
-eager launches, every sweep carrying hipExtLaunchKernel start/stop events),
-the time to the 1e-4 relative stopping test, the 20000 x 20000 roofline
-instance and the CPU oracle timed on a bounded sample.
+is printed with iterations/s at 4096^2 (`value`: whole graph replays, no
+events), the roofline of the sweep kernel on the 20000 x 20000 instance
+(3.2 GB, the HBM-bound size; a timed region of eager launches, every sweep
+carrying hipExtLaunchKernel start/stop events), the times to the 1e-4
+relative stopping test at 4096^2 and 20000^2, the precision forms, the
+batched solver and the CPU oracle timed on a bounded sample.
 """
 import argparse
 import json
@@ -56,7 +57,7 @@ def upload(inst):
 
 
 def pmc_summary(m, n):
-    return os.path.join(ROOT, "profiles", f"sweep_f32_{m}x{n}_pmc.txt")
+    return os.path.join(ROOT, "profiles", f"sweep_aux_f32_{m}x{n}.txt")
 
 
 def source_digest(path):
@@ -226,7 +227,8 @@ def precision_section(ctx, steps=200, warmup=20):
     return out
 
 
-def batch_section(ctx, count=512, iters=100, tol_rho0=2.0, tol=1e-4, n_seq=64):
+def batch_section(ctx, count=512, iters=100, tol_rho0=2.0, tol=1e-4, n_seq=32, do_tol=True,
+                  one_by_one=True):
     """512 ragged problems (m, n uniform in [64, 2048]): the tuner's schedules
     per size class (drot_tune_batched), a fixed number of iterations batched
     against the same problems one by one, and every problem solved to the
@@ -278,11 +280,11 @@ def batch_section(ctx, count=512, iters=100, tol_rho0=2.0, tol=1e-4, n_seq=64):
     log(f"batched steady state: {per_iter * 1e3:.3f} ms per iteration, {gbs_ss:.0f} GB/s "
         f"({100 * gbs_ss / HBM_PEAK_GBS:.1f}% of peak)")
     t0 = time.perf_counter()
-    for pr in probs:
+    for pr in (probs if one_by_one else []):
         drot.solve(pr["C"], pr["p"], pr["q"], pr["rho"], tol=0.0, max_iter=iters, check_every=50,
                    ctx=ctx)
     torch.cuda.synchronize()
-    t_seq = time.perf_counter() - t0
+    t_seq = time.perf_counter() - t0 if one_by_one else float("nan")
     gbs = 12.0 * entries * iters / t_batch / 1e9
     log(f"batch of {count} x {iters} iterations: {t_batch:.3f}s batched (tuned; untuned "
         f"{t_untuned:.3f}s) vs {t_seq:.3f}s one by one ({t_seq / t_batch:.1f}x), {gbs:.0f} GB/s "
@@ -294,6 +296,8 @@ def batch_section(ctx, count=512, iters=100, tol_rho0=2.0, tol=1e-4, n_seq=64):
            "steady_GBs": gbs_ss, "steady_frac": gbs_ss / HBM_PEAK_GBS,
            "tuner_seconds": t_tune, "tuned_classes": table,
            "workload": "config_batch: m, n ~ U[64, 2048], 2-D blob clouds, Dirichlet(1), float32"}
+    if not do_tol:
+        return out
     # every problem to the relative test
     for pr in probs:
         pr["rho"] = tol_rho0 / (pr["m"] + pr["n"])
@@ -543,13 +547,13 @@ def run_to_tol(ctx, bind, label, tol=1e-4, max_iter=3_000_000, chunk=8192):
             "eps_gap": r["eps_gap"]}
 
 
-def tol_forms_section(ctx, rho0=2.0, tol=1e-4, n_seq=64):
+def tol_forms_section(ctx, rho0=2.0, tol=1e-4, compensated=True):
     """Time to the 1e-4 relative test of the plain float32 form against the
-    reduced-byte forms (10000 x 15000) and the batched form (512 ragged
-    problems; the one-by-one comparison on the first n_seq of them)."""
+    reduced-byte forms at 10000 x 15000 (the batched form's is in the batch
+    section)."""
     import numpy as np
     import torch
-    from gen import config_batch, config_cube_3d
+    from gen import config_cube_3d
     from paper_2110_11738_amd import drot
     out = {"tol": tol, "rho0": rho0}
     inst = config_cube_3d(0)
@@ -570,6 +574,8 @@ def tol_forms_section(ctx, rho0=2.0, tol=1e-4, n_seq=64):
                                   drot.FLAG_COMPENSATED),
                                  ("bf16", drot.COST_BF16, (Cb,), 0),
                                  ("coords", drot.COST_COORDS, (xs, xt), 0)):
+        if name == "dense_f32_compensated" and not compensated:
+            continue
         cost = drot.make_cost(kind, C=C32 if kind == drot.COST_DENSE else Cb, xs=xs, xt=xt,
                               scale=scale)
 
@@ -578,46 +584,11 @@ def tol_forms_section(ctx, rho0=2.0, tol=1e-4, n_seq=64):
             ctx.bind_cost(m, n, cost, p, q, X, prm, keep=keep)
         forms[name] = run_to_tol(ctx, bind, f"{m}x{n} {name}", tol)
     out["precision_10000x15000"] = forms
+    d = forms["dense_f32"]["seconds_device"]
+    for name, r in forms.items():
+        r["ratio_to_dense_f32"] = r["seconds_device"] / d
     del C32, Cb, xs, xt, X
     torch.cuda.empty_cache()
-    # batched vs one by one
-    insts = config_batch(512)
-    probs = []
-    for I in insts:
-        probs.append({"C": drot.padded(torch.from_numpy(I.C.astype(np.float32)).cuda()),
-                      "p": torch.from_numpy(I.p.astype(np.float32)).cuda(),
-                      "q": torch.from_numpy(I.q.astype(np.float32)).cuda(),
-                      "rho": rho0 / (I.m + I.n), "tol": tol})
-    del insts
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rc, outs = drot.solve_batched(probs[:n_seq], max_iter=3_000_000, check_every=64, ctx=ctx)
-    torch.cuda.synchronize()
-    t_b_sub = time.perf_counter() - t0
-    it_sub = [o[1]["iters"] for o in outs]
-    del outs
-    log(f"batched {n_seq} to {tol:g}: {t_b_sub:.2f}s (iterations {min(it_sub)}..{max(it_sub)})")
-    t0 = time.perf_counter()
-    for k, pr in enumerate(probs[:n_seq]):
-        drot.solve(pr["C"], pr["p"], pr["q"], pr["rho"], tol=tol, max_iter=3_000_000,
-                   check_every=64, ctx=ctx)
-        if k % 16 == 15:
-            log(f"  one by one: {k + 1}/{n_seq}, {time.perf_counter() - t0:.0f}s")
-    torch.cuda.synchronize()
-    t_seq = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    rc, outs = drot.solve_batched(probs, max_iter=3_000_000, check_every=64, ctx=ctx)
-    torch.cuda.synchronize()
-    t_b_all = time.perf_counter() - t0
-    its = [o[1]["iters"] for o in outs]
-    n_conv = sum(1 for o in outs if o[1]["status"] == 0)
-    del outs
-    log(f"batched 512 to {tol:g}: {t_b_all:.2f}s ({n_conv} converged, iterations "
-        f"{min(its)}..{max(its)}); first {n_seq}: batched {t_b_sub:.2f}s vs one by one {t_seq:.2f}s")
-    out["batch"] = {"problems": len(probs), "seconds_batched_all": t_b_all, "converged": n_conv,
-                    "iters_min": min(its), "iters_max": max(its),
-                    "iters_mean": float(np.mean(its)), "subset": n_seq,
-                    "seconds_batched_subset": t_b_sub, "seconds_one_by_one_subset": t_seq}
     return out
 
 
@@ -710,8 +681,8 @@ def main():
                     help="skip timing the large instance to the 1e-4 test (about 3.5 minutes)")
     ap.add_argument("--tol-large-rho0", type=float, default=2.0)
     ap.add_argument("--tol-forms", action="store_true",
-                    help="time to 1e-4 of the reduced-byte and batched forms against plain float32 "
-                         "(minutes)")
+                    help="also time the compensated form to 1e-4 (the dense, bfloat16 and "
+                         "coordinate forms are timed by default)")
     ap.add_argument("--tol-forms-rho0", type=float, default=2.0)
     ap.add_argument("--paper-sizes", action="store_true",
                     help="the paper's runtime protocol at m = n from 100 to 20000")
@@ -719,6 +690,8 @@ def main():
                     help="skip every section before the large instance (profiling runs)")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the batched-solver section (profiling runs)")
+    ap.add_argument("--no-one-by-one", action="store_true",
+                    help="batch section: skip the one-by-one comparison (profiling runs)")
     ap.add_argument("--precision-only", action="store_true",
                     help="only the 10000 x 15000 precision section (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -750,7 +723,8 @@ def main():
         return
     if args.batch_only:
         out = {"metric": "batched DROT (profiling run)", "batch_only": True,
-               "batch": batch_section(ctx)}
+               "batch": batch_section(ctx, do_tol=not args.no_tol,
+                                      one_by_one=not args.no_one_by_one)}
         ctx.close()
         print(json.dumps(out), flush=True)
         return
@@ -862,7 +836,7 @@ def main():
     if not args.no_precision and not args.large_only:
         out["precision"] = precision_section(ctx)
     if not args.no_batch and not args.large_only:
-        out["batch"] = batch_section(ctx)
+        out["batch"] = batch_section(ctx, do_tol=not args.no_tol)
     if not args.no_small and not args.large_only:
         out["small"] = small_section(ctx)
 
@@ -917,8 +891,9 @@ def main():
     if args.paper_sizes:
         out["paper_sizes"] = paper_sizes_section(ctx)
 
-    if args.tol_forms:
-        out["time_to_tol_forms"] = tol_forms_section(ctx, rho0=args.tol_forms_rho0)
+    if not args.no_tol and not args.no_precision:
+        out["time_to_tol_forms"] = tol_forms_section(ctx, rho0=args.tol_forms_rho0,
+                                                     compensated=args.tol_forms)
 
     if args.calibrate_copy:
         calibrate_copy(torch, out)
