@@ -436,6 +436,44 @@ def small_section(ctx, sizes=(100, 128), iters=2000, warm=200):
     return out
 
 
+def mlp_section(dims=(2048, 512, 2048), batch=256, steps=50, warm=5):
+    """The warm-start network's kernels (bfloat16 MFMA GEMMs with fused
+    epilogues, Adam): a training step and a forward pass on random data,
+    milliseconds and dense matrix-core throughput (bfloat16 peak 2.5 PFLOP/s)."""
+    import numpy as np
+    import torch
+    from paper_2110_11738_amd import drot
+    i, h, o = dims
+    net = drot.MLP(i, h, o, max_batch=batch, seed=0)
+    rng = np.random.default_rng(7)
+    x = torch.tensor(rng.standard_normal((batch, i)).astype(np.float32), device="cuda")
+    t = torch.tensor(rng.standard_normal((batch, o)).astype(np.float32), device="cuda")
+    for _ in range(warm):
+        net.train_step(x, t, 1e-4)
+        net.forward(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.train_step(x, t, 1e-4)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.forward(x)
+    torch.cuda.synchronize()
+    ms_fwd = (time.perf_counter() - t0) * 1e3 / steps
+    macs = batch * (i * h + h * h + h * o)
+    fwd_flop, step_flop = 2 * macs, 2 * macs * 3 - 2 * batch * i * h  # no input gradient
+    net.close()
+    log(f"mlp {i}->{h}->{h}->{o}, batch {batch}: train step {ms_step:.3f} ms "
+        f"({step_flop / ms_step / 1e9:.1f} TFLOP/s), forward {ms_fwd:.3f} ms")
+    return {"dims": list(dims), "batch": batch, "train_step_ms": ms_step, "forward_ms": ms_fwd,
+            "train_step_TFLOPs": step_flop / ms_step / 1e9, "forward_TFLOPs": fwd_flop / ms_fwd / 1e9,
+            "forward_us_per_sample": ms_fwd * 1e3 / batch,
+            "note": "host-synchronous steps (the loss is read back every step): launch-bound at "
+                    "this size"}
+
+
 def phase_times(ctx, bind, reps=5):
     """Host wall time of the phases around the iteration: bind (validation,
     initialisation pass X_0 = p q^T with its sums, and the check of the
@@ -839,6 +877,7 @@ def main():
         out["batch"] = batch_section(ctx, do_tol=not args.no_tol)
     if not args.no_small and not args.large_only:
         out["small"] = small_section(ctx)
+        out["mlp"] = mlp_section()
 
     # ---- 20000^2 roofline instance ----------------------------------------------
     if not args.no_large and args.large > 0:

@@ -53,19 +53,34 @@ __host__ __device__ inline bf16 to_bf16(float f) {
 }
 
 // ---------------------------------------------------------------------------
-// C[M x N] = alpha * op(A)[M x K] * op(B)[K x N] + beta * C, bfloat16 inputs,
-// float32 accumulation and output.  A is stored row-major as M x K (TA = 0)
-// or K x M (TA = 1); B as K x N (TB = 0) or N x K (TB = 1).  A workgroup of
-// four waves computes a 64 x 64 tile, each wave a 32 x 32 block with the
-// 32x32x8 bfloat16 MFMA; K advances 32 at a time through LDS.
-// Requires M % 64 == N % 64 == K % 32 == 0 (checked on the host).
+// C[M x N] = op(A)[M x K] * op(B)[K x N] (+ beta * C), bfloat16 inputs,
+// float32 accumulation on the matrix cores (v_mfma_f32_32x32x8 bf16).  A is
+// stored row-major as M x K (TA = 0) or K x M (TA = 1); B as K x N (TB = 0)
+// or N x K (TB = 1).  A workgroup of four waves computes a 64 x 64 tile, each
+// wave a 32 x 32 block; K advances 32 at a time.  Every thread brings one
+// 16-byte piece (8 bfloat16 along the stored contiguous dimension) of each
+// operand tile into LDS, where both tiles are kept K-contiguous (As[m][k],
+// Bs[n][k]) so that each lane reads its 4-element fragments as 8 bytes.
+// Epilogues: EPI 0 stores the product (adding beta * C); EPI 1 adds the bias
+// of the column, applies ReLU when `relu`, and stores the float32 result and
+// its bfloat16 copy (a layer's forward step); EPI 2 keeps the product where
+// `gate` > 0 and zeroes it elsewhere, storing float32 and bfloat16 (the
+// backward step through a ReLU).
+// Requires M % 64 == N % 64 == K % 32 == 0, leading dimensions multiples of
+// 8 and 16-byte aligned operands (checked on the host).
 // ---------------------------------------------------------------------------
-template <int TA, int TB>
+typedef short v8s __attribute__((ext_vector_type(8)));
+
+template <int TA, int TB, int EPI>
 __global__ __launch_bounds__(256) void gemm_bf16(const bf16* __restrict__ A, const bf16* __restrict__ B,
                                                  float* __restrict__ C, int M, int N, int K, int lda,
-                                                 int ldb, int ldc, float alpha, float beta) {
-  __shared__ bf16 As[64][32 + 4];
-  __shared__ bf16 Bs[32][64 + 4];
+                                                 int ldb, int ldc, float beta,
+                                                 const float* __restrict__ bias,
+                                                 const float* __restrict__ gate,
+                                                 bf16* __restrict__ Cb, int relu) {
+  constexpr int LDK = 32 + 8;  // K-contiguous rows, 80 bytes: 16-byte stores stay aligned
+  __shared__ __align__(16) bf16 As[64][LDK];
+  __shared__ __align__(16) bf16 Bs[64][LDK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   const int wr = wave >> 1, wc = wave & 1;
@@ -73,57 +88,56 @@ __global__ __launch_bounds__(256) void gemm_bf16(const bf16* __restrict__ A, con
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.f;
   for (int k0 = 0; k0 < K; k0 += 32) {
-    // 64 x 32 A tile and 32 x 64 B tile, 8 elements per thread each.
+    if (TA == 0) {  // row m0 + r of A, k0 + c .. + 7
+      const int r = tid >> 2, c = (tid & 3) * 8;
+      *reinterpret_cast<v8s*>(&As[r][c]) =
+          *reinterpret_cast<const v8s*>(A + (size_t)(m0 + r) * lda + k0 + c);
+    } else {        // row k0 + kr of the K x M storage, columns m0 + mc .. + 7
+      const int kr = tid >> 3, mc = (tid & 7) * 8;
+      const v8s v = *reinterpret_cast<const v8s*>(A + (size_t)(k0 + kr) * lda + m0 + mc);
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int e = tid + 256 * t;  // 0..2047
-      const int r = e >> 5, c = e & 31;         // A tile (row r of 64, col c of 32)
-      As[r][c] = TA ? A[(size_t)(k0 + c) * lda + (m0 + r)] : A[(size_t)(m0 + r) * lda + (k0 + c)];
-      const int br = e >> 6, bc = e & 63;       // B tile (row br of 32, col bc of 64)
-      Bs[br][bc] = TB ? B[(size_t)(n0 + bc) * ldb + (k0 + br)] : B[(size_t)(k0 + br) * ldb + (n0 + bc)];
+      for (int e = 0; e < 8; ++e) As[mc + e][kr] = (bf16)v[e];
+    }
+    if (TB == 1) {  // row n0 + r of the N x K storage, k0 + c .. + 7
+      const int r = tid >> 2, c = (tid & 3) * 8;
+      *reinterpret_cast<v8s*>(&Bs[r][c]) =
+          *reinterpret_cast<const v8s*>(B + (size_t)(n0 + r) * ldb + k0 + c);
+    } else {        // row k0 + kr of the K x N storage, columns n0 + nc .. + 7
+      const int kr = tid >> 3, nc = (tid & 7) * 8;
+      const v8s v = *reinterpret_cast<const v8s*>(B + (size_t)(k0 + kr) * ldb + n0 + nc);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) Bs[nc + e][kr] = (bf16)v[e];
     }
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < 32; kk += 8) {
-      v4s a, b;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        a[i] = (short)As[wr * 32 + (lane & 31)][kk + 4 * (lane >> 5) + i];
-        b[i] = (short)Bs[kk + 4 * (lane >> 5) + i][wc * 32 + (lane & 31)];
-      }
+      const v4s a = *reinterpret_cast<const v4s*>(&As[wr * 32 + (lane & 31)][kk + 4 * (lane >> 5)]);
+      const v4s b = *reinterpret_cast<const v4s*>(&Bs[wc * 32 + (lane & 31)][kk + 4 * (lane >> 5)]);
       acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
     }
     __syncthreads();
   }
   // lane holds column (lane % 32) and rows 8 (r / 4) + 4 (lane / 32) + r % 4
   const int col = n0 + wc * 32 + (lane & 31);
+  const float bcol = EPI == 1 ? bias[col] : 0.f;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int row = m0 + wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-    float* out = C + (size_t)row * ldc + col;
-    *out = alpha * acc[r] + (beta != 0.f ? beta * *out : 0.f);
+    const size_t o = (size_t)row * ldc + col;
+    if (EPI == 0) {
+      C[o] = acc[r] + (beta != 0.f ? beta * C[o] : 0.f);
+    } else {
+      float v = acc[r];
+      if (EPI == 1) {
+        v += bcol;
+        if (relu && !(v > 0.f)) v = 0.f;
+      } else if (!(gate[o] > 0.f)) {
+        v = 0.f;
+      }
+      C[o] = v;
+      Cb[o] = to_bf16(v);
+    }
   }
-}
-
-// y = act(z + bias) in float32, plus its bfloat16 copy.
-__global__ void bias_act(const float* __restrict__ z, const float* __restrict__ bias,
-                         float* __restrict__ y, bf16* __restrict__ yb, int rows, int cols, int relu) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)rows * cols) return;
-  float v = z[i] + bias[i % cols];
-  if (relu && !(v > 0.f)) v = 0.f;
-  y[i] = v;
-  yb[i] = to_bf16(v);
-}
-
-// dz = dh * [a > 0] (ReLU backward), float32 and bfloat16.
-__global__ void relu_back(const float* __restrict__ dh, const float* __restrict__ a,
-                          float* __restrict__ dz, bf16* __restrict__ dzb, int64_t count) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
-  const float v = a[i] > 0.f ? dh[i] : 0.f;
-  dz[i] = v;
-  dzb[i] = to_bf16(v);
 }
 
 // Mean squared error: dy = 2 (y - t) / count; per-block partial sums of
@@ -198,9 +212,9 @@ struct drot_mlp {
   float* g = nullptr;    // gradients (flat)
   float* m1 = nullptr;
   float* m2 = nullptr;
-  float *z[3] = {}, *a[3] = {};  // pre-activations (GEMM out) and activations
+  float* a[3] = {};  // activations (layer outputs)
   bf16 *ab[3] = {}, *xb = nullptr;
-  float *d[3] = {}, *dh = nullptr;
+  float* d[3] = {};  // gradients with respect to the pre-activations
   bf16 *db[3] = {};
   double* part = nullptr;
   double* part_host = nullptr;
@@ -212,13 +226,29 @@ namespace {
 int64_t layer_in(const drot_mlp* n, int l) { return l == 0 ? n->in : n->hid; }
 int64_t layer_out(const drot_mlp* n, int l) { return l == 2 ? n->out : n->hid; }
 
+// One GEMM launch (see gemm_bf16): epi 0 plain, 1 bias (+ ReLU), 2 ReLU gate.
 hipError_t gemm(const bf16* A, const bf16* B, float* C, int M, int N, int K, int lda, int ldb,
-                int ldc, int ta, int tb, float beta, hipStream_t s) {
+                int ldc, int ta, int tb, float beta, hipStream_t s, int epi = 0,
+                const float* bias = nullptr, const float* gate = nullptr, bf16* Cb = nullptr,
+                int relu = 0) {
   const dim3 grid(N / 64, M / 64), block(256);
-  if (!ta && !tb) hipLaunchKernelGGL((gemm_bf16<0, 0>), grid, block, 0, s, A, B, C, M, N, K, lda, ldb, ldc, 1.f, beta);
-  if (!ta && tb) hipLaunchKernelGGL((gemm_bf16<0, 1>), grid, block, 0, s, A, B, C, M, N, K, lda, ldb, ldc, 1.f, beta);
-  if (ta && !tb) hipLaunchKernelGGL((gemm_bf16<1, 0>), grid, block, 0, s, A, B, C, M, N, K, lda, ldb, ldc, 1.f, beta);
-  if (ta && tb) hipLaunchKernelGGL((gemm_bf16<1, 1>), grid, block, 0, s, A, B, C, M, N, K, lda, ldb, ldc, 1.f, beta);
+#define DROT_GEMM(TA_, TB_, E_)                                                              \
+  hipLaunchKernelGGL((gemm_bf16<TA_, TB_, E_>), grid, block, 0, s, A, B, C, M, N, K, lda, ldb, \
+                     ldc, beta, bias, gate, Cb, relu)
+  const int key = ta * 6 + tb * 3 + epi;
+  switch (key) {
+    case 0: DROT_GEMM(0, 0, 0); break;
+    case 1: DROT_GEMM(0, 0, 1); break;
+    case 2: DROT_GEMM(0, 0, 2); break;
+    case 3: DROT_GEMM(0, 1, 0); break;
+    case 4: DROT_GEMM(0, 1, 1); break;
+    case 5: DROT_GEMM(0, 1, 2); break;
+    case 6: DROT_GEMM(1, 0, 0); break;
+    case 7: DROT_GEMM(1, 0, 1); break;
+    case 8: DROT_GEMM(1, 0, 2); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef DROT_GEMM
   return hipGetLastError();
 }
 
@@ -237,10 +267,9 @@ int forward(drot_mlp* n, int B, const float* x, hipStream_t s) {
   const bf16* inp = n->xb;
   for (int l = 0; l < 3; ++l) {
     const int K = (int)layer_in(n, l), N = (int)layer_out(n, l);
-    MHIP(gemm(inp, n->wb + n->off_w[l], n->z[l], B, N, K, K, K, N, 0, 1, 0.f, s));
-    hipLaunchKernelGGL(bias_act, dim3(nblk((int64_t)B * N)), dim3(256), 0, s, n->z[l],
-                       n->w + n->off_b[l], n->a[l], n->ab[l], B, N, l < 2 ? 1 : 0);
-    MHIP(hipGetLastError());
+    // a_l = act(x_l W_l^T + b_l) and its bfloat16 copy, from the epilogue
+    MHIP(gemm(inp, n->wb + n->off_w[l], n->a[l], B, N, K, K, K, N, 0, 1, 0.f, s, 1,
+              n->w + n->off_b[l], nullptr, n->ab[l], l < 2 ? 1 : 0));
     inp = n->ab[l];
   }
   return DROT_OK;
@@ -260,11 +289,9 @@ int backward(drot_mlp* n, int B, const float* t, double* loss, hipStream_t s) {
     hipLaunchKernelGGL(col_sum, dim3(nblk(N)), dim3(256), 0, s, n->d[l], n->g + n->off_b[l], B, N);
     MHIP(hipGetLastError());
     if (l > 0) {
-      // dh_{l-1} = dZ_l W_l (B x K), then through the ReLU of layer l-1
-      MHIP(gemm(n->db[l], n->wb + n->off_w[l], n->dh, B, K, N, N, K, K, 0, 0, 0.f, s));
-      hipLaunchKernelGGL(relu_back, dim3(nblk((int64_t)B * K)), dim3(256), 0, s, n->dh,
-                         n->a[l - 1], n->d[l - 1], n->db[l - 1], (int64_t)B * K);
-      MHIP(hipGetLastError());
+      // dZ_{l-1} = (dZ_l W_l) * [a_{l-1} > 0] (B x K), the ReLU gate in the epilogue
+      MHIP(gemm(n->db[l], n->wb + n->off_w[l], n->d[l - 1], B, K, N, N, K, K, 0, 0, 0.f, s, 2,
+                nullptr, n->a[l - 1], n->db[l - 1]));
     }
   }
   MHIP(hipMemcpyAsync(n->part_host, n->part, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
@@ -330,14 +357,12 @@ int drot_mlp_create(drot_mlp** out, int device, int in, int hidden, int outd, in
             hipMalloc(&n->m1, sizeof(float) * o) == hipSuccess &&
             hipMalloc(&n->m2, sizeof(float) * o) == hipSuccess &&
             hipMalloc(&n->xb, sizeof(bf16) * (size_t)max_batch * in) == hipSuccess &&
-            hipMalloc(&n->dh, sizeof(float) * (size_t)max_batch * hidden) == hipSuccess &&
             hipMalloc(&n->part, sizeof(double) * nblk((int64_t)max_batch * outd)) == hipSuccess &&
             hipHostMalloc((void**)&n->part_host, sizeof(double) * nblk((int64_t)max_batch * outd),
                           hipHostMallocDefault) == hipSuccess;
   for (int l = 0; l < 3 && ok; ++l) {
     const size_t c = (size_t)max_batch * layer_out(n, l);
-    ok = hipMalloc(&n->z[l], sizeof(float) * c) == hipSuccess &&
-         hipMalloc(&n->a[l], sizeof(float) * c) == hipSuccess &&
+    ok = hipMalloc(&n->a[l], sizeof(float) * c) == hipSuccess &&
          hipMalloc(&n->ab[l], sizeof(bf16) * c) == hipSuccess &&
          hipMalloc(&n->d[l], sizeof(float) * c) == hipSuccess &&
          hipMalloc(&n->db[l], sizeof(bf16) * c) == hipSuccess;
@@ -359,11 +384,11 @@ int drot_mlp_destroy(drot_mlp* n) {
   if (!n) return DROT_OK;
   (void)hipSetDevice(n->device);
   (void)hipDeviceSynchronize();
-  void* bufs[] = {n->w, n->wb, n->g, n->m1, n->m2, n->xb, n->dh, n->part};
+  void* bufs[] = {n->w, n->wb, n->g, n->m1, n->m2, n->xb, n->part};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (int l = 0; l < 3; ++l) {
-    void* lb[] = {n->z[l], n->a[l], n->ab[l], n->d[l], n->db[l]};
+    void* lb[] = {n->a[l], n->ab[l], n->d[l], n->db[l]};
     for (void* b : lb)
       if (b) (void)hipFree(b);
   }

@@ -166,27 +166,35 @@ def solved_data(ctx, C, ps, qs, tol, rho0, path, tag, quiet=False):
 
 def run(n_train: int, n_test: int, epochs: int, batch: int, lr: float, tol: float,
         hidden: int = 512, seed: int = 0, rho0: float | None = None, data: str | None = None,
-        canon: bool = True, side: int = SIDE, quiet: bool = False) -> dict:
+        canon: bool = True, side: int = SIDE, quiet: bool = False,
+        train_files: list | None = None) -> dict:
+    """Solve (or load, from generate() files) the training pairs, train the
+    network, and solve the held-out pairs cold and warm.  The warm time per
+    pair includes the network's forward pass (its share of the batched
+    inference)."""
     import torch
     N = side * side
     ctx = drot.Context(0)
     Cn = grid_cost(side)
     C = torch.tensor(Cn, dtype=torch.float32, device="cuda")
     t0 = time.time()
+    if train_files:
+        T, it_train, st_train = load_targets(train_files, side)
+        n_train = len(T) if n_train <= 0 else min(n_train, len(T))
+        T, it_train, st_train = T[:n_train], it_train[:n_train], st_train[:n_train]
     ps, qs = make_pairs(n_train, 0, side=side)
     pt, qt = make_pairs(n_test, 1, side=side)
     log(f"generated {n_train} + {n_test} pairs in {time.time() - t0:.1f}s")
     t0 = time.time()
-    mu, nu, it_train, _, _, st_train = solved_data(ctx, C, ps, qs, tol, rho0, data, "train",
-                                                        quiet)
+    if not train_files:
+        mu, nu, it_train, _, _, st_train = solved_data(ctx, C, ps, qs, tol, rho0, data, "train",
+                                                       quiet)
+        mu, nu = mu.astype(np.float64), nu.astype(np.float64)
+        if canon:
+            mu, nu = canonical(Cn, mu, nu)
+        T = gauge_fix(mu, nu)
     t_data = time.time() - t0
-    mu, nu = mu.astype(np.float64), nu.astype(np.float64)
-    if canon:
-        t0 = time.time()
-        mu, nu = canonical(Cn, mu, nu)
-        log(f"canonical targets in {time.time() - t0:.1f}s")
     X = features(ps, qs)
-    T = gauge_fix(mu, nu)
     # Standardised targets (per output: training mean and one global scale).
     t_mean = T.mean(axis=0, keepdims=True)
     t_scale = float(T.std()) or 1.0
@@ -200,7 +208,10 @@ def run(n_train: int, n_test: int, epochs: int, batch: int, lr: float, tol: floa
     mu_c, nu_c, it_c, s_c, obj_c, st_c = solved_data(ctx, C, pt, qt, tol, rho0, data, "test",
                                                        quiet)
     mu_c, nu_c = mu_c.astype(np.float64), nu_c.astype(np.float64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     mu_hat, nu_hat = predict(net, features(pt, qt), max(batch, 64))
+    t_infer = (time.perf_counter() - t0) / n_test  # host-side features and transfers included
     mu_hat = mu_hat * t_scale + t_mean[0, :N]
     nu_hat = nu_hat * t_scale + t_mean[0, N:]
     mu_w, nu_w, it_w, s_w, obj_w, st_w = solve_pairs(ctx, C, pt, qt, tol, mu0=mu_hat, nu0=nu_hat,
@@ -222,6 +233,9 @@ def run(n_train: int, n_test: int, epochs: int, batch: int, lr: float, tol: floa
         "cold_iters_mean": float(it_c.mean()), "cold_iters_median": float(np.median(it_c)),
         "warm_iters_mean": float(it_w_eff.mean()), "warm_iters_median": float(np.median(it_w_eff)),
         "cold_seconds_mean": float(s_c.mean()), "warm_seconds_mean": float(s_w.mean()),
+        "inference_seconds_per_pair": t_infer,
+        "warm_seconds_with_inference_mean": float(s_w.mean()) + t_infer,
+        "seconds_ratio_with_inference": (float(s_w.mean()) + t_infer) / float(s_c.mean()),
         "warm_fallbacks": int(fallback.sum()),
         "objective_rel_diff_warm_vs_cold_max": float(rel_obj.max()),
         "iteration_ratio_mean": float(it_w_eff.mean() / it_c.mean()),
@@ -229,6 +243,50 @@ def run(n_train: int, n_test: int, epochs: int, batch: int, lr: float, tol: floa
     net.close()
     ctx.close()
     return report
+
+
+def generate(out: str, count: int, start: int, split: int, tol: float, rho0: float | None,
+             chunk: int = 512, side: int = SIDE, canon: bool = True) -> None:
+    """Solve pairs [start, start + count) of a split with the batched solver
+    and save their gauge-fixed (double c-transformed) duals as float16 with
+    the iteration counts and statuses, `chunk` pairs per batch, the file
+    rewritten after every batch.  The histograms are not stored: they are
+    regenerated from their seeds."""
+    import torch
+    ctx = drot.Context(0)
+    Cn = grid_cost(side)
+    C = torch.tensor(Cn, dtype=torch.float32, device="cuda")
+    T, its, sts = [], [], []
+    t0 = time.time()
+    for s0 in range(start, start + count, chunk):
+        n = min(chunk, start + count - s0)
+        ps, qs = make_pairs(n, split, start=s0, side=side)
+        mu, nu, it, _, _, st = solve_pairs(ctx, C, ps, qs, tol, rho0=rho0, chunk=n, quiet=True)
+        if canon:
+            mu, nu = canonical(Cn, mu, nu)
+        T.append(gauge_fix(mu, nu).astype(np.float16))
+        its.append(it)
+        sts.append(st)
+        np.savez(out, targets=np.concatenate(T), iters=np.concatenate(its),
+                 status=np.concatenate(sts), start=start, split=split, tol=tol,
+                 rho0=-1.0 if rho0 is None else rho0, side=side)
+        log(f"pairs {start}..{s0 + n} of split {split}: mean iterations "
+            f"{np.concatenate(its).mean():.0f}, {time.time() - t0:.0f}s")
+    ctx.close()
+
+
+def load_targets(paths, side: int = SIDE):
+    """Concatenate generate() files of split 0 (contiguous ranges from 0)."""
+    T, its, sts, n = [], [], [], 0
+    for path in sorted(paths, key=lambda q: int(np.load(q)["start"])):
+        z = np.load(path)
+        if int(z["start"]) != n or int(z["split"]) != 0 or int(z["side"]) != side:
+            raise ValueError(f"{path}: not the next contiguous range of training pairs")
+        T.append(z["targets"].astype(np.float32))
+        its.append(z["iters"])
+        sts.append(z["status"])
+        n += len(z["targets"])
+    return np.concatenate(T), np.concatenate(its), np.concatenate(sts)
 
 
 def main():
@@ -244,9 +302,17 @@ def main():
     ap.add_argument("--data", default=None, help=".npz cache of the solved training and test pairs")
     ap.add_argument("--raw-targets", action="store_true", help="learn the solver's duals as returned")
     ap.add_argument("--side", type=int, default=SIDE, help="grid side (histograms of side^2 cells)")
+    ap.add_argument("--gen", default=None, help="only solve training pairs into this .npz")
+    ap.add_argument("--gen-start", type=int, default=0)
+    ap.add_argument("--train-files", default=None,
+                    help="comma-separated generate() files with the training targets")
     args = ap.parse_args()
+    if args.gen:
+        generate(args.gen, args.train, args.gen_start, 0, args.tol, args.rho0, side=args.side)
+        return
     rep = run(args.train, args.test, args.epochs, args.batch, args.lr, args.tol, args.hidden,
-              rho0=args.rho0, data=args.data, canon=not args.raw_targets, side=args.side)
+              rho0=args.rho0, data=args.data, canon=not args.raw_targets, side=args.side,
+              train_files=args.train_files.split(",") if args.train_files else None)
     print(json.dumps(rep), flush=True)
 
 
