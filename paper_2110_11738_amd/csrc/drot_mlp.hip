@@ -66,7 +66,10 @@ __host__ __device__ inline bf16 to_bf16(float f) {
 // its bfloat16 copy (a layer's forward step); EPI 2 keeps the product where
 // `gate` > 0 and zeroes it elsewhere, storing float32 and bfloat16 (the
 // backward step through a ReLU).
-// Requires M % 64 == N % 64 == K % 32 == 0, leading dimensions multiples of
+// EPI 3 (split K): workgroup z of the grid's third dimension multiplies the
+// slice [z ks, (z + 1) ks) of K and stores its raw product at C + z M ldc;
+// splitk_reduce adds the slices in order and applies the epilogue.
+// Requires M % 64 == N % 64 == ks % 32 == 0, leading dimensions multiples of
 // 8 and 16-byte aligned operands (checked on the host).
 // ---------------------------------------------------------------------------
 typedef short v8s __attribute__((ext_vector_type(8)));
@@ -77,7 +80,7 @@ __global__ __launch_bounds__(256) void gemm_bf16(const bf16* __restrict__ A, con
                                                  int ldb, int ldc, float beta,
                                                  const float* __restrict__ bias,
                                                  const float* __restrict__ gate,
-                                                 bf16* __restrict__ Cb, int relu) {
+                                                 bf16* __restrict__ Cb, int relu, int ks) {
   constexpr int LDK = 32 + 8;  // K-contiguous rows, 80 bytes: 16-byte stores stay aligned
   __shared__ __align__(16) bf16 As[64][LDK];
   __shared__ __align__(16) bf16 Bs[64][LDK];
@@ -87,7 +90,8 @@ __global__ __launch_bounds__(256) void gemm_bf16(const bf16* __restrict__ A, con
   v16f acc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-  for (int k0 = 0; k0 < K; k0 += 32) {
+  const int kb = blockIdx.z * ks, ke = kb + ks;
+  for (int k0 = kb; k0 < ke; k0 += 32) {
     if (TA == 0) {  // row m0 + r of A, k0 + c .. + 7
       const int r = tid >> 2, c = (tid & 3) * 8;
       *reinterpret_cast<v8s*>(&As[r][c]) =
@@ -120,11 +124,14 @@ __global__ __launch_bounds__(256) void gemm_bf16(const bf16* __restrict__ A, con
   // lane holds column (lane % 32) and rows 8 (r / 4) + 4 (lane / 32) + r % 4
   const int col = n0 + wc * 32 + (lane & 31);
   const float bcol = EPI == 1 ? bias[col] : 0.f;
+  if (EPI == 3) C += (size_t)blockIdx.z * M * ldc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int row = m0 + wr * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
     const size_t o = (size_t)row * ldc + col;
-    if (EPI == 0) {
+    if (EPI == 3) {
+      C[o] = acc[r];
+    } else if (EPI == 0) {
       C[o] = acc[r] + (beta != 0.f ? beta * C[o] : 0.f);
     } else {
       float v = acc[r];
@@ -138,6 +145,34 @@ __global__ __launch_bounds__(256) void gemm_bf16(const bf16* __restrict__ A, con
       Cb[o] = to_bf16(v);
     }
   }
+}
+
+// The split-K sum: C = sum over z = 0, 1, ... of P[z] (M x N slices, leading
+// dimension N, added in that order), then GEMM epilogue EPI (0, 1 or 2).
+template <int EPI>
+__global__ __launch_bounds__(256) void splitk_reduce(const float* __restrict__ P, int S, int M,
+                                                     int N, float* __restrict__ C, int ldc,
+                                                     float beta, const float* __restrict__ bias,
+                                                     const float* __restrict__ gate,
+                                                     bf16* __restrict__ Cb, int relu) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)M * N) return;
+  const int row = (int)(i / N), col = (int)(i % N);
+  float v = P[i];
+  for (int z = 1; z < S; ++z) v += P[(size_t)z * M * N + i];
+  const size_t o = (size_t)row * ldc + col;
+  if (EPI == 0) {
+    C[o] = v + (beta != 0.f ? beta * C[o] : 0.f);
+    return;
+  }
+  if (EPI == 1) {
+    v += bias[col];
+    if (relu && !(v > 0.f)) v = 0.f;
+  } else if (!(gate[o] > 0.f)) {
+    v = 0.f;
+  }
+  C[o] = v;
+  Cb[o] = to_bf16(v);
 }
 
 // Mean squared error: dy = 2 (y - t) / count; per-block partial sums of
@@ -164,13 +199,40 @@ __global__ void mse_grad(const float* __restrict__ y, const float* __restrict__ 
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-// Column sums of a rows x cols float32 matrix (bias gradients), fixed order.
-__global__ void col_sum(const float* __restrict__ g, float* __restrict__ out, int rows, int cols) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= cols) return;
+// Column sums of a rows x cols float32 matrix (bias gradients), fixed order:
+// a workgroup owns 64 columns; its kColSlices waves each add the rows
+// congruent to the wave index (mod kColSlices), four loads in flight, and
+// wave 0 adds the slices' sums in slice order.
+constexpr int kColSlices = 16;
+__global__ __launch_bounds__(kColSlices * 64) void col_sum(const float* __restrict__ g,
+                                                           float* __restrict__ out, int rows,
+                                                           int cols) {
+  __shared__ float part[kColSlices][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + lane;
   float s = 0.f;
-  for (int r = 0; r < rows; ++r) s += g[(int64_t)r * cols + j];
-  out[j] = s;
+  if (j < cols) {
+    int r = w;
+    for (; r + 3 * kColSlices < rows; r += 4 * kColSlices) {
+      const float v0 = g[(int64_t)r * cols + j];
+      const float v1 = g[(int64_t)(r + kColSlices) * cols + j];
+      const float v2 = g[(int64_t)(r + 2 * kColSlices) * cols + j];
+      const float v3 = g[(int64_t)(r + 3 * kColSlices) * cols + j];
+      s += v0;
+      s += v1;
+      s += v2;
+      s += v3;
+    }
+    for (; r < rows; r += kColSlices) s += g[(int64_t)r * cols + j];
+  }
+  part[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && j < cols) {
+    float t = 0.f;
+#pragma unroll
+    for (int k = 0; k < kColSlices; ++k) t += part[k][lane];
+    out[j] = t;
+  }
 }
 
 __global__ void cast_bf16(const float* __restrict__ x, bf16* __restrict__ y, int64_t count) {
@@ -218,6 +280,7 @@ struct drot_mlp {
   bf16 *db[3] = {};
   double* part = nullptr;
   double* part_host = nullptr;
+  float* ksplit = nullptr;  // split-K partial products (kSplitCap floats)
   int64_t step = 0;
 };
 
@@ -226,29 +289,63 @@ namespace {
 int64_t layer_in(const drot_mlp* n, int l) { return l == 0 ? n->in : n->hid; }
 int64_t layer_out(const drot_mlp* n, int l) { return l == 2 ? n->out : n->hid; }
 
-// One GEMM launch (see gemm_bf16): epi 0 plain, 1 bias (+ ReLU), 2 ReLU gate.
+// Split-K workspace: S slices of M x N with S (M / 64) (N / 64) <= 256.
+constexpr size_t kSplitCap = (size_t)256 * 64 * 64;
+
+// K slices for an M x N x K product: while the grid has fewer than 256
+// workgroups (one per compute unit), halve the depth per workgroup, down to
+// 128 (four K steps of 32), up to 8 slices.
+int split_k(int M, int N, int K) {
+  const int grid = (M / 64) * (N / 64);
+  int S = 1;
+  while (S < 8 && grid * S * 2 <= 256 && K % (64 * S) == 0 && K / (2 * S) >= 128) S *= 2;
+  return S;
+}
+
+// One GEMM (see gemm_bf16): epi 0 plain, 1 bias (+ ReLU), 2 ReLU gate; split
+// over K (partials in `ws`, then splitk_reduce) when the tile grid alone
+// would leave compute units idle.
 hipError_t gemm(const bf16* A, const bf16* B, float* C, int M, int N, int K, int lda, int ldb,
-                int ldc, int ta, int tb, float beta, hipStream_t s, int epi = 0,
+                int ldc, int ta, int tb, float beta, hipStream_t s, float* ws, int epi = 0,
                 const float* bias = nullptr, const float* gate = nullptr, bf16* Cb = nullptr,
                 int relu = 0) {
-  const dim3 grid(N / 64, M / 64), block(256);
-#define DROT_GEMM(TA_, TB_, E_)                                                              \
-  hipLaunchKernelGGL((gemm_bf16<TA_, TB_, E_>), grid, block, 0, s, A, B, C, M, N, K, lda, ldb, \
-                     ldc, beta, bias, gate, Cb, relu)
-  const int key = ta * 6 + tb * 3 + epi;
-  switch (key) {
+  const int S = ws ? split_k(M, N, K) : 1;
+  const dim3 grid(N / 64, M / 64, S), block(256);
+  float* dst = S > 1 ? ws : C;
+  const int ldd = S > 1 ? N : ldc;
+  const int e = S > 1 ? 3 : epi;
+  const int ks = K / S;
+#define DROT_GEMM(TA_, TB_, E_)                                                                \
+  hipLaunchKernelGGL((gemm_bf16<TA_, TB_, E_>), grid, block, 0, s, A, B, dst, M, N, K, lda, ldb, \
+                     ldd, beta, bias, gate, Cb, relu, ks)
+  switch (ta * 8 + tb * 4 + e) {
     case 0: DROT_GEMM(0, 0, 0); break;
     case 1: DROT_GEMM(0, 0, 1); break;
     case 2: DROT_GEMM(0, 0, 2); break;
-    case 3: DROT_GEMM(0, 1, 0); break;
-    case 4: DROT_GEMM(0, 1, 1); break;
-    case 5: DROT_GEMM(0, 1, 2); break;
-    case 6: DROT_GEMM(1, 0, 0); break;
-    case 7: DROT_GEMM(1, 0, 1); break;
-    case 8: DROT_GEMM(1, 0, 2); break;
+    case 3: DROT_GEMM(0, 0, 3); break;
+    case 4: DROT_GEMM(0, 1, 0); break;
+    case 5: DROT_GEMM(0, 1, 1); break;
+    case 6: DROT_GEMM(0, 1, 2); break;
+    case 7: DROT_GEMM(0, 1, 3); break;
+    case 8: DROT_GEMM(1, 0, 0); break;
+    case 9: DROT_GEMM(1, 0, 1); break;
+    case 10: DROT_GEMM(1, 0, 2); break;
+    case 11: DROT_GEMM(1, 0, 3); break;
     default: return hipErrorInvalidValue;
   }
 #undef DROT_GEMM
+  if (S == 1) return hipGetLastError();
+  const unsigned nb = (unsigned)(((int64_t)M * N + 255) / 256);
+#define DROT_RED(E_)                                                                          \
+  hipLaunchKernelGGL((splitk_reduce<E_>), dim3(nb), block, 0, s, ws, S, M, N, C, ldc, beta, bias, \
+                     gate, Cb, relu)
+  switch (epi) {
+    case 0: DROT_RED(0); break;
+    case 1: DROT_RED(1); break;
+    case 2: DROT_RED(2); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef DROT_RED
   return hipGetLastError();
 }
 
@@ -268,7 +365,7 @@ int forward(drot_mlp* n, int B, const float* x, hipStream_t s) {
   for (int l = 0; l < 3; ++l) {
     const int K = (int)layer_in(n, l), N = (int)layer_out(n, l);
     // a_l = act(x_l W_l^T + b_l) and its bfloat16 copy, from the epilogue
-    MHIP(gemm(inp, n->wb + n->off_w[l], n->a[l], B, N, K, K, K, N, 0, 1, 0.f, s, 1,
+    MHIP(gemm(inp, n->wb + n->off_w[l], n->a[l], B, N, K, K, K, N, 0, 1, 0.f, s, n->ksplit, 1,
               n->w + n->off_b[l], nullptr, n->ab[l], l < 2 ? 1 : 0));
     inp = n->ab[l];
   }
@@ -285,13 +382,14 @@ int backward(drot_mlp* n, int B, const float* t, double* loss, hipStream_t s) {
     const int K = (int)layer_in(n, l), N = (int)layer_out(n, l);
     const bf16* inp = l == 0 ? n->xb : n->ab[l - 1];
     // dW_l = dZ_l^T x_l  (N x K);  db_l = column sums of dZ_l
-    MHIP(gemm(n->db[l], inp, n->g + n->off_w[l], N, K, B, N, K, K, 1, 0, 0.f, s));
-    hipLaunchKernelGGL(col_sum, dim3(nblk(N)), dim3(256), 0, s, n->d[l], n->g + n->off_b[l], B, N);
+    MHIP(gemm(n->db[l], inp, n->g + n->off_w[l], N, K, B, N, K, K, 1, 0, 0.f, s, n->ksplit));
+    hipLaunchKernelGGL(col_sum, dim3((N + 63) / 64), dim3(kColSlices * 64), 0, s, n->d[l],
+                       n->g + n->off_b[l], B, N);
     MHIP(hipGetLastError());
     if (l > 0) {
       // dZ_{l-1} = (dZ_l W_l) * [a_{l-1} > 0] (B x K), the ReLU gate in the epilogue
-      MHIP(gemm(n->db[l], n->wb + n->off_w[l], n->d[l - 1], B, K, N, N, K, K, 0, 0, 0.f, s, 2,
-                nullptr, n->a[l - 1], n->db[l - 1]));
+      MHIP(gemm(n->db[l], n->wb + n->off_w[l], n->d[l - 1], B, K, N, N, K, K, 0, 0, 0.f, s,
+                n->ksplit, 2, nullptr, n->a[l - 1], n->db[l - 1]));
     }
   }
   MHIP(hipMemcpyAsync(n->part_host, n->part, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
@@ -358,6 +456,7 @@ int drot_mlp_create(drot_mlp** out, int device, int in, int hidden, int outd, in
             hipMalloc(&n->m2, sizeof(float) * o) == hipSuccess &&
             hipMalloc(&n->xb, sizeof(bf16) * (size_t)max_batch * in) == hipSuccess &&
             hipMalloc(&n->part, sizeof(double) * nblk((int64_t)max_batch * outd)) == hipSuccess &&
+            hipMalloc(&n->ksplit, sizeof(float) * kSplitCap) == hipSuccess &&
             hipHostMalloc((void**)&n->part_host, sizeof(double) * nblk((int64_t)max_batch * outd),
                           hipHostMallocDefault) == hipSuccess;
   for (int l = 0; l < 3 && ok; ++l) {
@@ -384,7 +483,7 @@ int drot_mlp_destroy(drot_mlp* n) {
   if (!n) return DROT_OK;
   (void)hipSetDevice(n->device);
   (void)hipDeviceSynchronize();
-  void* bufs[] = {n->w, n->wb, n->g, n->m1, n->m2, n->xb, n->part};
+  void* bufs[] = {n->w, n->wb, n->g, n->m1, n->m2, n->xb, n->part, n->ksplit};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (int l = 0; l < 3; ++l) {
