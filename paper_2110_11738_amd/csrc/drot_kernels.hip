@@ -1333,7 +1333,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a, const int ct, con
               if (!RAGGED || nv[c] == VEC) {
                 store_chunk<T, VEC, NT>(X + i * a.g.ldx + jc[c], outv);
               } else {
-                for (int e = 0; e < nv[c]; ++e) X[i * a.g.ldx + jc[c] + e] = outv[e];
+#pragma unroll
+                for (int e = 0; e < VEC; ++e)
+                  if (e < nv[c]) X[i * a.g.ldx + jc[c] + e] = outv[e];
               }
             }
           }
