@@ -296,6 +296,9 @@ __device__ __forceinline__ void iter_sums(const double* bp, int nb, int col_wgs,
     double v[B][8];
 #pragma unroll
     for (int u = 0; u < B; ++u) {
+#pragma unroll
+      for (int s = 0; s < 8; ++s) v[u][s] = 0.0;
+      if (k0 + u * kWave >= nb) continue;  // wave-uniform: no load in this block
       const int k = k0 + u * kWave + lane;
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
@@ -303,7 +306,7 @@ __device__ __forceinline__ void iter_sums(const double* bp, int nb, int col_wgs,
         if (s < 3) use = use && k >= col_wgs;
         else if (s < 6) use = use && k < col_wgs;
         const double* ptr = bp + (int64_t)slot[s] * nb + k;
-        v[u][s] = use ? (AGENT ? load_agent(ptr) : *ptr) : 0.0;
+        if (use) v[u][s] = AGENT ? load_agent(ptr) : *ptr;
       }
     }
 #pragma unroll
@@ -1128,15 +1131,15 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a, const int ct, con
   double shift_d = 0.0;
   if (is_iter(MODE)) {
     if (a.st_prev) {
-      // Wave 0 closes the previous iteration (the sums' loads issued first,
-      // the record's next) and hands the shift and the stop decision to the
-      // other waves through LDS.
+      // Wave 0 closes the previous iteration and hands the shift and the
+      // stop decision to the other waves through LDS.
       __shared__ double closing[2];
       if (threadIdx.x < kWave) {
+        // The record's loads first, so that they are in flight with the sums'.
+        const StateIn pv = load_state(a.st_prev);
         double w[8];
         iter_sums<false>(a.bp_prev, (int)aux_workgroups(m, n),
                          (int)((n + kAuxCols - 1) / kAuxCols), w);
-        const StateIn pv = load_state(a.st_prev);
         double sh = 0.0, stop = 1.0;
         if (pv.done) {
           if (blockIdx.x == 0 && threadIdx.x == 0) *a.st = *a.st_prev;
