@@ -930,7 +930,7 @@ def main():
     if args.paper_sizes:
         out["paper_sizes"] = paper_sizes_section(ctx)
 
-    if not args.no_tol and not args.no_precision:
+    if not args.no_tol and not args.no_precision and not args.large_only:
         out["time_to_tol_forms"] = tol_forms_section(ctx, rho0=args.tol_forms_rho0,
                                                      compensated=args.tol_forms)
 
