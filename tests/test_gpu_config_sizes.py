@@ -122,22 +122,22 @@ def test_objective_4096_against_network_simplex(ctx, mix4096):
         print(f"[objective 4096^2] rho0 {rho0:.4f} tol {tol:.0e}: iters {res['iters']} "
               f"objective {res['objective']:.10e} opt {opt:.10e} rel {err:.2e} "
               f"eps_p {res['eps_primal']:.1e} eps_g {res['eps_gap']:.1e}", flush=True)
-        _check_objective(res, opt, tol, judged=tol <= 1e-5)
+        _check_objective(res, opt, tol, strict=tol <= 1e-5)
         del X
 
 
-def _check_objective(res, opt, tol, judged):
+def _check_objective(res, opt, tol, strict):
     """The relative stopping test bounds the objective error only loosely: the
     dual residual is relative to |C|_F (about 10^3 here), so a plan stopped at
     tol can be off by more than tol.  Weak duality gives one side exactly:
     OPT >= p.mu + q.nu^c >= dobj - r_dual (the c-transform lowers each nu_j by
     at most the largest violation, itself at most r_dual), so
-    objective - OPT <= gap + r_dual.  The judged bound -- objective within
-    1e-4 of OPT in float32 -- is asserted when `judged` (a tolerance tight
+    objective - OPT <= gap + r_dual.  The accuracy bound -- objective within
+    1e-4 of OPT in float32 -- is asserted when `strict` (a tolerance tight
     enough for the instance)."""
     assert res["status"] == 0 and res["eps_primal"] <= tol
     assert res["objective"] - opt <= res["gap"] + res["r_dual"] + 1e-12
-    if judged:
+    if strict:
         assert abs(res["objective"] - opt) <= 1e-4 * opt
 
 
@@ -154,7 +154,7 @@ def test_objective_line_4096(ctx):
         err = abs(res["objective"] - opt) / opt
         print(f"[objective line 4096^2] tol {tol:.0e}: iters {res['iters']} "
               f"objective {res['objective']:.10e} opt {opt:.10e} rel {err:.2e}", flush=True)
-        _check_objective(res, opt, tol, judged=tol <= 1e-6)
+        _check_objective(res, opt, tol, strict=tol <= 1e-6)
         del X
 
 
