@@ -832,7 +832,7 @@ def main():
         out["copy_reference"] = copy_reference()
 
         if not args.no_tune:
-            tile = tuned_tile(ctx, bind, 256)
+            tile = tuned_tile(ctx, bind, 2048)
             rt = measure(ctx, dense_binder(ctx, C, p, q, inst.rho, args, tile), args.steps, args.warmup)
             ach_t = alg_bytes / (rt["sweep_ms"] * 1e-3) / 1e9
             out["tuned"] = {"tile_rows": tile[0], "tile_chunks": tile[1], "tile_groups": tile[2],
