@@ -387,7 +387,10 @@ int drot_tune_batched(drot_ctx *ctx, int32_t count, int dtype, const drot_proble
  * cores (32x32x8 bfloat16 MFMA, float32 accumulation).  Widths and batches
  * are multiples of 64.  The flat parameter vector is [W1, b1, W2, b2, W3, b3]
  * with W_l stored row-major as out_l x in_l.  x, y, t and grad are device
- * float32 arrays, row-major batch x width. */
+ * float32 arrays, row-major batch x width.  The network owns its device
+ * buffers (parameters, Adam moments, activations for max_batch rows and a
+ * 4 MiB split-K workspace) and reuses them on every call: calls on one
+ * network must be ordered (one stream, or synchronised), not concurrent. */
 typedef struct drot_mlp drot_mlp;
 int drot_mlp_create(drot_mlp **mlp, int device, int in_dim, int hidden, int out_dim,
                     int max_batch, uint64_t seed);
