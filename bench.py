@@ -377,10 +377,11 @@ def paper_sizes_section(ctx, sizes=(100, 200, 500, 1000, 2000, 5000, 10000, 2000
     out = []
     for m in sizes:
         inst = paper_protocol(0, m, rho0=1.0 / math.log(m))
-        C = torch.from_numpy(inst.C.astype(np.float32)).cuda()
+        # rows on 128-byte cache lines, as the main workload's
+        C = drot.padded(torch.from_numpy(inst.C.astype(np.float32)).cuda())
         p = torch.from_numpy(inst.p.astype(np.float32)).cuda()
         q = torch.from_numpy(inst.q.astype(np.float32)).cuda()
-        X = torch.empty_like(C)
+        X = drot.empty_plan(m, m, torch.float32, "cuda")
         rho = inst.rho
         del inst
         rates = []
@@ -416,10 +417,11 @@ def small_section(ctx, sizes=(100, 128), iters=2000, warm=200):
     out = []
     for m in sizes:
         inst = paper_protocol(0, m, rho0=1.0 / math.log(m))
-        C = torch.from_numpy(inst.C.astype(np.float32)).cuda()
+        # rows on 128-byte cache lines, as the main workload's
+        C = drot.padded(torch.from_numpy(inst.C.astype(np.float32)).cuda())
         p = torch.from_numpy(inst.p.astype(np.float32)).cuda()
         q = torch.from_numpy(inst.q.astype(np.float32)).cuda()
-        X = torch.empty_like(C)
+        X = drot.empty_plan(m, m, torch.float32, "cuda")
         row = {"m": m, "n": m}
         for name, tr in (("one_workgroup", 0), ("sweep_aux", 16)):
             ctx.bind(C, p, q, X, drot.make_params(inst.rho, 0.0, warm + iters + 1, tile_rows=tr))
