@@ -279,6 +279,22 @@ def batch_section(ctx, count=512, iters=100, tol_rho0=2.0, tol=1e-4, n_seq=32, d
     gbs_ss = 12.0 * entries / per_iter / 1e9
     log(f"batched steady state: {per_iter * 1e3:.3f} ms per iteration, {gbs_ss:.0f} GB/s "
         f"({100 * gbs_ss / HBM_PEAK_GBS:.1f}% of peak)")
+    # the same with the default schedule (a fresh context has an empty tuner cache)
+    ctx_u = drot.Context(ctx.device)
+    drot.solve_batched(probs[:8], max_iter=5, ctx=ctx_u)
+    tu = []
+    for k in (iters, 3 * iters):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, outs = drot.solve_batched(probs, max_iter=k, check_every=50, ctx=ctx_u)
+        torch.cuda.synchronize()
+        tu.append(time.perf_counter() - t0)
+        del outs
+    ctx_u.close()
+    per_iter_u = (tu[1] - tu[0]) / (2 * iters)
+    gbs_su = 12.0 * entries / per_iter_u / 1e9
+    log(f"batched steady state, default schedule: {per_iter_u * 1e3:.3f} ms per iteration, "
+        f"{gbs_su:.0f} GB/s ({100 * gbs_su / HBM_PEAK_GBS:.1f}% of peak)")
     t0 = time.perf_counter()
     for pr in (probs if one_by_one else []):
         drot.solve(pr["C"], pr["p"], pr["q"], pr["rho"], tol=0.0, max_iter=iters, check_every=50,
@@ -294,6 +310,8 @@ def batch_section(ctx, count=512, iters=100, tol_rho0=2.0, tol=1e-4, n_seq=32, d
            "seconds_one_by_one": t_seq, "speedup": t_seq / t_batch, "achieved_GBs": gbs,
            "frac": gbs / HBM_PEAK_GBS, "steady_ms_per_iter": per_iter * 1e3,
            "steady_GBs": gbs_ss, "steady_frac": gbs_ss / HBM_PEAK_GBS,
+           "steady_ms_per_iter_default_schedule": per_iter_u * 1e3,
+           "steady_frac_default_schedule": gbs_su / HBM_PEAK_GBS,
            "tuner_seconds": t_tune, "tuned_classes": table,
            "workload": "config_batch: m, n ~ U[64, 2048], 2-D blob clouds, Dirichlet(1), float32"}
     if not do_tol:

@@ -1071,6 +1071,135 @@ __global__ __launch_bounds__(kBlock) void aux_batch_kernel(const SweepArgs* __re
   aux_body<T, MODE, false, true>(a, (int)w.y, (int)aux_workgroups(a.g.m, a.g.n));
 }
 
+// The batched iteration's aux work items, one per wave, four per workgroup
+// (the batch's items are small: a few row groups deep, so a whole workgroup
+// per item spent most of its life on fixed costs).  Per item the same
+// quantities as aux_body<T, kIter, false, true> with these orders: column
+// items split the row groups over G1 lane groups (each adds its range in
+// order) and add the G1 sums in order; row items add their strips in order;
+// every lane then takes the step of its column or row.
+template <typename T>
+__device__ __forceinline__ void aux_wave_iter(const SweepArgs& a, const int b, const int nb,
+                                              double* __restrict__ red) {
+  using P = typename PartialOf<T, kIter>::type;
+  constexpr int CW = 16 / sizeof(P);   // columns per 16-byte chunk
+  constexpr int NCH = kAuxCols / CW;   // chunks per item
+  constexpr int G1 = kWave / NCH;      // row-group ranges per item (= CW)
+  using V = typename VecOf<P, CW>::type;
+  static_assert(kAuxCols == kWave && kAuxRows == kWave, "one entry per lane");
+
+  const StateIn sv = load_state(a.st);
+  const int64_t m = a.g.m, n = a.g.n;
+  const int col_wgs = (int)((n + kAuxCols - 1) / kAuxCols);
+  const int lane = threadIdx.x & (kWave - 1);
+  const bool is_col = b < col_wgs;
+
+  int64_t idx = -1;
+  double w0 = 0.0, w1 = 0.0, tot = 0.0;
+  if (is_col) {
+    const int64_t j0 = (int64_t)b * kAuxCols;
+    const int ch = lane % NCH, grp = lane / NCH;
+    const int n_rg = a.g.n_rg;
+    const int r0 = (int)((int64_t)n_rg * grp / G1), r1 = (int)((int64_t)n_rg * (grp + 1) / G1);
+    const P* cp = static_cast<const P*>(a.colpart) + j0 + ch * CW;
+    double sv4[CW];
+#pragma unroll
+    for (int e = 0; e < CW; ++e) sv4[e] = 0.0;
+    sum_strided<8>(reinterpret_cast<const V*>(cp), a.g.ldcp / CW, r0, r1, sv4);
+#pragma unroll
+    for (int e = 0; e < CW; ++e) red[grp * kAuxCols + ch * CW + e] = sv4[e];
+    const int64_t j = j0 + lane;
+    if (j < n) {
+      idx = j;
+      w0 = (double)static_cast<const T*>(a.q)[j];
+      w1 = a.b[j];
+    }
+  } else {
+    const int64_t i = (int64_t)(b - col_wgs) * kAuxRows + lane;
+    if (i < m) {
+      typedef P P1 __attribute__((ext_vector_type(1)));
+      double u[1] = {0.0};
+      sum_strided<8>(reinterpret_cast<const P1*>(static_cast<const P*>(a.rowpart) + i), m, 0,
+                     a.g.n_ct, u);
+      tot = u[0];
+      idx = i;
+      w0 = (double)static_cast<const T*>(a.p)[i];
+      w1 = a.a[i];
+    }
+  }
+  // A fixed slice of the sweep's tile scalars.
+  double st0 = 0.0, st1 = 0.0;
+  {
+    const int64_t nt = (int64_t)a.g.n_ct * a.g.n_rg;
+    const int64_t t0 = nt * b / nb, t1 = nt * (b + 1) / nb;
+    for (int64_t tb = t0; tb < t1; tb += 4 * kWave) {
+      double v0[4], v1[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t t = tb + u * kWave + lane;
+        v0[u] = t < t1 ? a.tiles[t * kTileSlots + kTs0] : 0.0;
+        v1[u] = t < t1 ? a.tiles[t * kTileSlots + kTs1] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        st0 += v0[u];
+        st1 += v1[u];
+      }
+    }
+  }
+  if (sv.done) return;
+  // The column sums cross lanes of this wave through LDS.
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (is_col && idx >= 0) {
+    tot = red[lane];
+#pragma unroll
+    for (int g = 1; g < G1; ++g) tot += red[g * kAuxCols + lane];
+  }
+  double* const accv = pick(is_col, a.b, a.a);      // a_i or b_j
+  double* const d64 = pick(is_col, a.psi64, a.phi64);
+  T* const dT = static_cast<T*>(pick(is_col, a.psiT, a.phiT));
+  const double len = is_col ? (double)m : (double)n;
+  double e0 = 0.0, e1 = 0.0, e2 = 0.0;
+  if (idx >= 0) {
+    const double res = tot - w0;
+    const double d = (w1 - 2.0 * res) / len;
+    accv[idx] = w1 - res;
+    d64[idx] = d;
+    dT[idx] = (T)d;
+    e0 = res;
+    e1 = res * res;
+    e2 = w0 * d;
+  }
+  double w[5] = {e0, e1, e2, st0, st1};
+  wave_sum_n(w);
+  if (lane == 0) {
+    double* const bp = a.blockpart + b;
+    const int64_t sb = is_col ? kSS : kSR;
+    store_agent(bp + (sb + 0) * nb, w[0]);
+    store_agent(bp + (sb + 1) * nb, w[1]);
+    store_agent(bp + (sb + 2) * nb, w[2]);
+    store_agent(bp + (int64_t)kST0 * nb, w[3]);
+    store_agent(bp + (int64_t)kST1 * nb, w[4]);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void aux_batch_iter_kernel(const SweepArgs* __restrict__ args,
+                                                                const uint2* __restrict__ work,
+                                                                int64_t n_aux) {
+  constexpr int CW = 16 / sizeof(typename PartialOf<T, kIter>::type);
+  __shared__ double red[kWaves][CW * kAuxCols];  // per wave: CW row-group ranges x 64 columns
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int64_t item = (int64_t)blockIdx.x * kWaves + wave;
+  if (item >= n_aux) return;
+  const uint2 w = work[item];
+  const SweepArgs a = args[__builtin_amdgcn_readfirstlane(w.x)];  // private copy, as above
+  aux_wave_iter<T>(a, (int)__builtin_amdgcn_readfirstlane(w.y), (int)aux_workgroups(a.g.m, a.g.n),
+                   red[wave]);
+}
+
 // Per-lane accumulator of the sweep.  Plain: a running sum in the partial
 // type.  Compensated (float32 iteration with DROT_FLAG_COMPENSATED): a
 // Neumaier (improved Kahan-Babuska) pair of floats, so that a lane's sum over
@@ -1713,8 +1842,12 @@ hipError_t sweep_batch_mode(const TileCfg& t, const SweepArgs* args, const uint2
 template <typename T, int MODE>
 void batch_aux(const SweepArgs* args, const uint2* aux_work, int64_t n_aux, int n_prob,
                hipStream_t s) {
-  hipLaunchKernelGGL((aux_batch_kernel<T, MODE>), dim3((unsigned)n_aux), dim3(kBlock), 0, s, args,
-                     aux_work);
+  if constexpr (MODE == kIter)
+    hipLaunchKernelGGL((aux_batch_iter_kernel<T>), dim3((unsigned)((n_aux + kWaves - 1) / kWaves)),
+                       dim3(kBlock), 0, s, args, aux_work, n_aux);
+  else
+    hipLaunchKernelGGL((aux_batch_kernel<T, MODE>), dim3((unsigned)n_aux), dim3(kBlock), 0, s, args,
+                       aux_work);
   hipLaunchKernelGGL((finish_batch_kernel<MODE>), dim3((unsigned)n_prob), dim3(kWave), 0, s, args);
 }
 
